@@ -1,0 +1,372 @@
+"""FP64 CPU oracle for ADSampling inside an IVF scan.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package.  It shares no code
+with the GPU library (``paper_2303_09855_amd``): neither imports the other, and
+the only common inputs come from the seeded generators in ``synthdata``.
+
+What it computes, each function citing the passage it follows:
+
+* :func:`make_rotation` -- Section 3.1: a random orthogonal matrix obtained by
+  orthonormalising a Gaussian matrix (QR, sign-fixed so the result is Haar);
+* :func:`rotate` -- y = P x (Section 3.1, the transformation of data and query
+  vectors);
+* :func:`brute_knn` -- the exact KNN query of Section 2.1 (ground truth);
+* :func:`probes` -- IVF probe selection, the N_probe nearest centroids
+  (Section 2.2.2);
+* :func:`dco_batch` -- Definition 2.1 by FDScanning, Algorithm 1
+  (ADSampling) or PDScanning (Section 6.1) for a fixed threshold;
+* :func:`ivf_search` -- the IVF scan with a KNN max-heap (Section 2.2.2), with
+  ADSampling as its DCO (IVF+, Section 4).  IVF++ (Section 5.2) changes only the
+  memory layout and gives the same result, so one oracle covers both;
+* :func:`recall`, :func:`distance_ratio`, :func:`dims_ratio` -- the metrics of
+  Section 6.1 (Performance Metrics).
+
+All arithmetic is in float64.  The scan and DCO loops are plain sequential C
+(``ads_oracle.c``), threaded over queries only.
+
+Pins (tests/test_oracle_pins.py): orthogonality and Haar sign symmetry of P,
+norm preservation, the row-sampling identity (Eq. 2), the exact-distance case
+d = D, no false positives (Lemma 3.2), eps0 = inf equal to FDScanning and to a
+full sort, monotonicity in eps0, the exact Beta law of the single-test failure
+probability, and hand-derived golden cases.  Absolute QPS and dims fractions
+are parity unpinned (the paper prints them only in figures).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_BUILD = os.path.join(_HERE, "_build")
+_SO = os.path.join(_BUILD, "libads_oracle.so")
+_SRC = os.path.join(_HERE, "ads_oracle.c")
+
+METHOD_ADS, METHOD_FDS, METHOD_PDS = 0, 1, 2
+
+# ---------------------------------------------------------------------------
+# build / load
+# ---------------------------------------------------------------------------
+
+
+def build() -> str:
+    """Compile the C part with gcc (always recompiles)."""
+    os.makedirs(_BUILD, exist_ok=True)
+    tmp = _SO + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC,
+           "-lm", "-lpthread"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _SO)
+    return _SO
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_SO):
+        build()
+    lib = ctypes.CDLL(_SO)
+    dp = ctypes.POINTER(ctypes.c_double)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    u8p = ctypes.POINTER(ctypes.c_uint8)
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.orc_ads_dco.argtypes = [dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_int, ip, dp]
+    lib.orc_ads_dco.restype = ctypes.c_int
+    lib.orc_fds_dco.argtypes = [dp, dp, ctypes.c_int, ctypes.c_double, dp]
+    lib.orc_fds_dco.restype = ctypes.c_int
+    lib.orc_pds_dco.argtypes = [dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ip, dp]
+    lib.orc_pds_dco.restype = ctypes.c_int
+    lib.orc_dco_batch.argtypes = [dp, ctypes.c_int, dp, i64p, ctypes.c_int64, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_int, ctypes.c_int, u8p, dp, i32p,
+                                  u8p, ctypes.c_double]
+    lib.orc_dco_batch.restype = None
+    lib.orc_ivf_search.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, i64p, i64p, i64p, i32p,
+                                   i32p, ctypes.c_int, i32p, ctypes.c_int, ctypes.c_double,
+                                   ctypes.c_int, ctypes.c_int, i64p, dp, i64p, ctypes.c_int]
+    lib.orc_ivf_search.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _p(a: np.ndarray, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+# ---------------------------------------------------------------------------
+# Section 3.1: random orthogonal transformation
+# ---------------------------------------------------------------------------
+
+
+def make_rotation(gaussian: np.ndarray) -> np.ndarray:
+    """Orthonormalise a Gaussian matrix (Section 3.1, footnote on random projection).
+
+    Householder QR (LAPACK via numpy), then Q <- Q diag(sign(diag R)) so that
+    Q is Haar distributed.  Returns P64 with y = P64 @ x.
+    """
+    g = np.asarray(gaussian, dtype=np.float64)
+    qm, rm = np.linalg.qr(g)
+    s = np.sign(np.diag(rm))
+    s[s == 0] = 1.0
+    return qm * s[None, :]
+
+
+def rotate(x: np.ndarray, P64: np.ndarray) -> np.ndarray:
+    """y = P x for every row x (float64)."""
+    return np.asarray(x, dtype=np.float64) @ P64.T
+
+
+# ---------------------------------------------------------------------------
+# Section 2.1: exact KNN (ground truth)
+# ---------------------------------------------------------------------------
+
+
+def exact_dist(x: np.ndarray, q: np.ndarray) -> np.ndarray:
+    """Distances ||x_i - q|| in float64, difference form."""
+    d = np.asarray(x, dtype=np.float64) - np.asarray(q, dtype=np.float64)[None, :]
+    return np.sqrt(np.einsum("ij,ij->i", d, d))
+
+
+def brute_knn(x: np.ndarray, queries: np.ndarray, K: int, screen: int = 64,
+              chunk: int = 65536, qchunk: int = 512) -> tuple[np.ndarray, np.ndarray]:
+    """Exact top-K by (distance, id) for every query, float64.
+
+    A float64 GEMM-form screen keeps the best K + screen candidates per query;
+    their distances are then recomputed in difference form and sorted by
+    (distance, id).  The distances returned are exact; when more than
+    ``screen`` objects tie with the K-th, the ids among those ties are a valid
+    choice but not necessarily the lowest ones (recall is tie-aware).
+    """
+    x = np.asarray(x, dtype=np.float32)
+    qall = np.asarray(queries, dtype=np.float64)
+    n = x.shape[0]
+    nq = qall.shape[0]
+    keep = min(n, K + screen)
+    ids = np.empty((nq, K), dtype=np.int64)
+    dist = np.empty((nq, K))
+    for qs0 in range(0, nq, qchunk):
+        qs = qall[qs0:qs0 + qchunk]
+        m = qs.shape[0]
+        best_s = np.full((m, keep), np.inf)
+        best_i = np.zeros((m, keep), dtype=np.int64)
+        qn = np.einsum("ij,ij->i", qs, qs)
+        for s in range(0, n, chunk):
+            e = min(n, s + chunk)
+            xb = x[s:e].astype(np.float64)
+            xn = np.einsum("ij,ij->i", xb, xb)
+            sc = xn[None, :] - 2.0 * (qs @ xb.T) + qn[:, None]
+            if sc.shape[1] > keep:
+                part = np.argpartition(sc, keep - 1, axis=1)[:, :keep]
+                sc_i = part + s
+                sc = np.take_along_axis(sc, part, 1)
+            else:
+                sc_i = np.broadcast_to(np.arange(s, e), sc.shape)
+            allv = np.concatenate([best_s, sc], axis=1)
+            alli = np.concatenate([best_i, sc_i], axis=1)
+            part = np.argpartition(allv, keep - 1, axis=1)[:, :keep]
+            best_s = np.take_along_axis(allv, part, 1)
+            best_i = np.take_along_axis(alli, part, 1)
+        for j in range(m):
+            i = qs0 + j
+            cand = best_i[j]
+            dv = exact_dist(x[cand], qs[j])
+            order = np.lexsort((cand, dv))
+            kk = min(K, len(order))
+            ids[i, :kk] = cand[order[:kk]]
+            dist[i, :kk] = dv[order[:kk]]
+            ids[i, kk:] = -1
+            dist[i, kk:] = np.inf
+    return ids, dist
+
+
+# ---------------------------------------------------------------------------
+# Section 2.2.2: IVF probe selection
+# ---------------------------------------------------------------------------
+
+
+def probes(q_rot: np.ndarray, c_rot: np.ndarray, nprobe: int) -> tuple[np.ndarray, np.ndarray]:
+    """The nprobe nearest centroids per query, ascending by (distance, list id).
+
+    Returns (list ids [nq, nprobe] int32, squared distances [nq, nlist] float64).
+    """
+    q = np.asarray(q_rot, dtype=np.float64)
+    c = np.asarray(c_rot, dtype=np.float64)
+    d2 = np.empty((q.shape[0], c.shape[0]))
+    for i in range(q.shape[0]):
+        diff = c - q[i][None, :]
+        d2[i] = np.einsum("ij,ij->i", diff, diff)
+    ids = np.empty((q.shape[0], nprobe), dtype=np.int32)
+    ar = np.arange(c.shape[0])
+    for i in range(q.shape[0]):
+        ids[i] = np.lexsort((ar, d2[i]))[:nprobe]
+    return ids, d2
+
+
+# ---------------------------------------------------------------------------
+# Definition 2.1 / Algorithm 1: DCOs with a fixed threshold
+# ---------------------------------------------------------------------------
+
+
+def ads_dco(o: np.ndarray, q: np.ndarray, r: float, eps0: float, delta_d: int):
+    """One ADSampling DCO (Algorithm 1). Returns (positive, dist, dims)."""
+    lib = _load()
+    o = np.ascontiguousarray(o, dtype=np.float64)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    dims = ctypes.c_int(0)
+    dist = ctypes.c_double(0.0)
+    pos = lib.orc_ads_dco(_p(o, ctypes.c_double), _p(q, ctypes.c_double), o.shape[0],
+                          float(r), float(eps0), int(delta_d), ctypes.byref(dims),
+                          ctypes.byref(dist))
+    return int(pos), dist.value, dims.value
+
+
+def fds_dco(o: np.ndarray, q: np.ndarray, r: float):
+    """One FDScanning DCO (Section 2.1). Returns (positive, dist)."""
+    lib = _load()
+    o = np.ascontiguousarray(o, dtype=np.float64)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    dist = ctypes.c_double(0.0)
+    pos = lib.orc_fds_dco(_p(o, ctypes.c_double), _p(q, ctypes.c_double), o.shape[0],
+                          float(r), ctypes.byref(dist))
+    return int(pos), dist.value
+
+
+def dco_batch(base_rot: np.ndarray, q_rot: np.ndarray, rows: np.ndarray, r: float,
+              eps0: float, delta_d: int, method: int = METHOD_ADS, band_rel: float = 1e-5):
+    """DCOs of query q against base rows ``rows`` with a fixed threshold r.
+
+    Returns dict(mask uint8, dist float64 (+inf for negatives), dims int32,
+    band uint8: 1 where the decision lies within band_rel of a test boundary).
+    """
+    lib = _load()
+    base = np.ascontiguousarray(base_rot, dtype=np.float64)
+    q = np.ascontiguousarray(q_rot, dtype=np.float64)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    m = rows.shape[0]
+    mask = np.zeros(m, dtype=np.uint8)
+    dist = np.zeros(m)
+    dims = np.zeros(m, dtype=np.int32)
+    band = np.zeros(m, dtype=np.uint8)
+    lib.orc_dco_batch(_p(base, ctypes.c_double), base.shape[1], _p(q, ctypes.c_double),
+                      _p(rows, ctypes.c_int64), m, float(r), float(eps0), int(delta_d),
+                      int(method), _p(mask, ctypes.c_uint8), _p(dist, ctypes.c_double),
+                      _p(dims, ctypes.c_int32), _p(band, ctypes.c_uint8), float(band_rel))
+    return {"mask": mask, "dist": dist, "dims": dims, "band": band}
+
+
+# ---------------------------------------------------------------------------
+# Section 2.2.2 + Section 4: the IVF scan (IVF, IVF+, IVF*)
+# ---------------------------------------------------------------------------
+
+
+def lists_from_assignment(assign: np.ndarray, nlist: int):
+    """Inverted lists: (offsets [nlist+1], member ids in ascending id order)."""
+    assign = np.asarray(assign, dtype=np.int64)
+    order = np.argsort(assign, kind="stable")
+    counts = np.bincount(assign, minlength=nlist)
+    off = np.zeros(nlist + 1, dtype=np.int64)
+    np.cumsum(counts, out=off[1:])
+    return off, order.astype(np.int64)
+
+
+def ivf_search(base_rot: np.ndarray, q_rot: np.ndarray, list_off: np.ndarray,
+               list_ids: np.ndarray, probe_ids: np.ndarray, K, eps0: float, delta_d: int,
+               method: int = METHOD_ADS, nprobe=None, threads: int = 0,
+               row_of_id=None, k_max: int | None = None):
+    """Sequential IVF scan per query (threads over queries only).
+
+    base_rot rows are addressed by ``row_of_id[id]`` (identity if None), so a
+    caller may pass only the rows of the probed lists.  K and nprobe may be
+    scalars or per-query arrays.  Returns (ids [nq,k_max], dist [nq,k_max],
+    stats [nq,3] = DCOs, sampled dims, positives).
+    """
+    lib = _load()
+    base = np.ascontiguousarray(base_rot, dtype=np.float64)
+    qs = np.ascontiguousarray(q_rot, dtype=np.float64)
+    nq, D = qs.shape
+    probe_ids = np.ascontiguousarray(probe_ids, dtype=np.int32)
+    nprobe_max = probe_ids.shape[1]
+    if nprobe is None:
+        nprobe = nprobe_max
+    npr = np.ascontiguousarray(np.broadcast_to(np.asarray(nprobe, dtype=np.int32), (nq,)))
+    Ks = np.ascontiguousarray(np.broadcast_to(np.asarray(K, dtype=np.int32), (nq,)))
+    if k_max is None:
+        k_max = int(Ks.max()) if nq else 0
+    list_off = np.ascontiguousarray(list_off, dtype=np.int64)
+    list_ids = np.ascontiguousarray(list_ids, dtype=np.int64)
+    if row_of_id is None:
+        rows = list_ids.copy()
+    else:
+        rows = np.ascontiguousarray(np.asarray(row_of_id, dtype=np.int64)[list_ids])
+    out_ids = np.zeros((nq, k_max), dtype=np.int64)
+    out_dist = np.zeros((nq, k_max))
+    stats = np.zeros((nq, 3), dtype=np.int64)
+    if threads <= 0:
+        threads = os.cpu_count() or 1
+    rc = lib.orc_ivf_search(_p(base, ctypes.c_double), _p(qs, ctypes.c_double), nq, D,
+                            _p(list_off, ctypes.c_int64), _p(rows, ctypes.c_int64),
+                            _p(list_ids, ctypes.c_int64), _p(probe_ids, ctypes.c_int32),
+                            _p(npr, ctypes.c_int32), nprobe_max, _p(Ks, ctypes.c_int32),
+                            int(k_max), float(eps0), int(delta_d), int(method),
+                            _p(out_ids, ctypes.c_int64), _p(out_dist, ctypes.c_double),
+                            _p(stats, ctypes.c_int64), int(threads))
+    if rc != 0:
+        raise MemoryError("oracle ivf_search failed to allocate")
+    return out_ids, out_dist, stats
+
+
+# ---------------------------------------------------------------------------
+# Section 6.1: metrics
+# ---------------------------------------------------------------------------
+
+
+def recall(ret_ids: np.ndarray, ret_dist_exact: np.ndarray, gt_dist: np.ndarray, K) -> float:
+    """Mean recall@K, tie-aware.
+
+    A returned object counts as a retrieved ground-truth neighbour when its
+    exact distance is at most the exact K-th ground-truth distance (objects
+    tied at that distance are interchangeable); the count is capped at K.
+    """
+    nq = ret_ids.shape[0]
+    Ks = np.broadcast_to(np.asarray(K), (nq,))
+    tot = 0.0
+    for i in range(nq):
+        k = int(Ks[i])
+        if k == 0:
+            tot += 1.0
+            continue
+        kth = gt_dist[i, k - 1]
+        valid = ret_ids[i, :k] >= 0
+        hit = np.count_nonzero(valid & (ret_dist_exact[i, :k] <= kth))
+        tot += min(hit, k) / k
+    return tot / nq
+
+
+def distance_ratio(ret_dist_exact: np.ndarray, gt_dist: np.ndarray, K) -> float:
+    """Average distance ratio: mean over ranks of dis(returned_i) / dis(gt_i) (0/0 := 1)."""
+    nq = ret_dist_exact.shape[0]
+    Ks = np.broadcast_to(np.asarray(K), (nq,))
+    vals = []
+    for i in range(nq):
+        k = int(Ks[i])
+        a = ret_dist_exact[i, :k]
+        b = gt_dist[i, :k]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            r = np.where((a == 0) & (b == 0), 1.0, a / b)
+        vals.append(np.mean(r) if k else 1.0)
+    return float(np.mean(vals))
+
+
+def dims_ratio(stats: np.ndarray, D: int) -> float:
+    """Total sampled dimensions over D times the number of DCOs."""
+    s = np.asarray(stats)
+    return float(s[:, 1].sum()) / float(D * max(1, s[:, 0].sum()))
