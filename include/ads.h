@@ -1,0 +1,267 @@
+/*
+ * ads.h -- C ABI of the MI355X (gfx950) ADSampling-IVF library.
+ *
+ * ADSampling (Gao & Long, SIGMOD 2023) decides a distance comparison
+ * operation (DCO, Definition 2.1: is dis(o, q) <= r, and if so what is dis)
+ * by sampling coordinates of randomly rotated vectors incrementally and
+ * stopping as soon as a hypothesis test rejects dis <= r (Algorithm 1,
+ * Sections 3.1-3.3).  This library runs it inside an IVF candidate scan
+ * (IVF+, Section 4) over a dimension-blocked list layout (IVF++, Section 5.2).
+ *
+ * Conventions for every entry point:
+ *   - Pointers are DEVICE pointers unless the argument says "host".
+ *   - Matrices are row-major and contiguous ([rows][cols]).
+ *   - The rotation is y = P x with P a [D][D] row-major orthogonal matrix, so a
+ *     batch of row vectors X is rotated as X * P^T (Section 3.1, Eq. 2).
+ *   - Distances are Euclidean (not squared), as in Definition 2.1; the kernels
+ *     compare squared values internally.
+ *   - Calls are asynchronous on the given HIP stream unless stated otherwise;
+ *     the caller keeps every buffer alive until the stream has passed the call.
+ *   - Arguments are validated on the host before anything is launched.  On a
+ *     failed validation the call returns a negative status, writes nothing and
+ *     sets a thread-local message readable with ads_last_error().
+ *   - A HIP error raised by a launch (or left pending by earlier asynchronous
+ *     work) is returned as ADS_EHIP.
+ *   - No C++ exception crosses this interface.
+ */
+#ifndef ADS_H
+#define ADS_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ADS_OK = 0,
+    ADS_EINVAL = -1,        /* invalid argument (message in ads_last_error) */
+    ADS_ENOMEM = -2,        /* device or host allocation failed */
+    ADS_EHIP = -3,          /* HIP runtime / launch error */
+    ADS_EUNSUPPORTED = -4   /* valid request this build does not support */
+} ads_status;
+
+typedef enum {
+    ADS_F32 = 0,            /* rotated vectors stored as float32 */
+    ADS_BF16 = 1,           /* stored as bfloat16 (round to nearest even) */
+    ADS_F16 = 2             /* stored as IEEE half (round to nearest even) */
+} ads_dtype;
+
+typedef enum {
+    ADS_METHOD_ADSAMPLING = 0,  /* Algorithm 1 with the test of Section 3.2 */
+    ADS_METHOD_FDSCANNING = 1,  /* full-dimension distance then compare (Section 2.1) */
+    ADS_METHOD_PDSCANNING = 2   /* partial-distance early stop on raw coordinates (Section 6.1) */
+} ads_method;
+
+/* Opaque index.  Device-resident, owned by the library, read-only after
+ * ads_ivf_build returns, released by ads_index_free. */
+typedef struct ads_index ads_index;
+
+/* Host-side description of an index. */
+typedef struct {
+    int64_t n;              /* number of stored vectors */
+    int32_t D;              /* dimensionality */
+    int32_t nlist;          /* number of inverted lists */
+    int32_t delta_d;        /* block width of the stored layout */
+    int32_t storage;        /* ads_dtype of the blocked layout */
+    int32_t has_fp32_copy;  /* 1 if a float32 row copy is kept (rerank / dco source) */
+    int32_t max_list;       /* largest list size */
+    int64_t device_bytes;   /* device memory held by the index */
+} ads_index_desc;
+
+/* Counters accumulated by ads_search / ads_dco_batch into a caller buffer of
+ * ADS_NSTATS int64 values on the device (never reset by the library). */
+enum {
+    ADS_STAT_DCOS = 0,          /* distance comparison operations */
+    ADS_STAT_DIMS = 1,          /* coordinates sampled over all DCOs */
+    ADS_STAT_POSITIVES = 2,     /* DCOs that returned positive */
+    ADS_STAT_BYTES = 3,         /* bytes of stored vector data the DCOs needed */
+    ADS_NSTATS = 4
+};
+
+/* --------------------------------------------------------------------------
+ * Rotation (Section 3.1).
+ * -------------------------------------------------------------------------- */
+
+/*
+ * ads_make_rotation -- HOST function.  Orthonormalises a Gaussian matrix into
+ * the random orthogonal transformation of Section 3.1 (the paper obtains it
+ * by orthonormalising a matrix of i.i.d. standard Gaussians, Section 3.1
+ * footnote; Section 6.1 generates it once in the index phase).
+ *   gaussian  host [D][D] float64, i.i.d. N(0,1) entries (caller's draw).
+ *   D         >= 1.
+ *   P_out     host [D][D] float32: P with y = P x (rows of P are the sampled
+ *             directions).  Householder QR in float64, columns of Q scaled by
+ *             sign(diag R) so that P is Haar distributed.
+ *   P64_out   host [D][D] float64 copy of the same matrix, or NULL.
+ * Errors: ADS_EINVAL for NULL inputs or D < 1; ADS_ENOMEM.  Synchronous.
+ */
+ads_status ads_make_rotation(const double *gaussian, int32_t D, float *P_out, double *P64_out);
+
+/*
+ * ads_rotate -- Y = X * P^T, i.e. y = P x for every row (Section 3.1, Eq. 2),
+ * on the matrix cores (FP32 MFMA, FP32 accumulation).
+ *   P   device [D][D] float32.   X device [n][D] float32.   Y device [n][D]
+ *   float32 (must not alias X).  n >= 0 (n == 0 is a no-op), 1 <= D, D % 4 == 0.
+ */
+ads_status ads_rotate(const float *P, int32_t D, const float *X, int64_t n, float *Y,
+                      hipStream_t stream);
+
+/* --------------------------------------------------------------------------
+ * Index phase (Section 2.2.2 IVF buckets, Section 5.2 IVF++ layout).
+ * -------------------------------------------------------------------------- */
+
+/*
+ * ads_ivf_build -- builds the IVF index from a clustering supplied by the
+ * caller (in the paper the k-means clustering comes from an external library,
+ * Section 6.1; the index is the same for IVF, IVF+ and IVF++).
+ *   base       device [n][D] float32 raw vectors; n >= 1.
+ *   P          device [D][D] float32 rotation (copied into the index).
+ *   centroids  device [nlist][D] float32 raw-space list centres.
+ *   assign     device [n] int32 list id of every vector, in [0, nlist).
+ *   delta_d    block width of the stored layout: D % delta_d == 0 and
+ *              delta_d % 8 == 0 (a multiple of 4 suffices for ADS_F32).
+ *   storage    ads_dtype of the blocked layout.
+ *   keep_fp32  1 to keep a float32 copy of the rotated rows (required by the
+ *              low-precision rerank and by ads_dco_batch's row source).
+ *   out        host pointer receiving the new index.
+ * Layout: the rotated vectors of list l are stored as [block][vector][delta_d]
+ * (all vectors' first block contiguous, then the second block, ...): the
+ * cache-friendly arrangement of Section 5.2 generalised from two arrays to
+ * one array per block.  Within a list, vectors keep ascending id order.
+ * Synchronises the stream once (the list sizes are needed on the host).
+ * Errors: ADS_EINVAL (sizes, ids out of range), ADS_ENOMEM, ADS_EHIP.
+ */
+ads_status ads_ivf_build(const float *base, int64_t n, int32_t D, const float *P,
+                         const float *centroids, int32_t nlist, const int32_t *assign,
+                         int32_t delta_d, int32_t storage, int32_t keep_fp32,
+                         hipStream_t stream, ads_index **out);
+
+/* ads_index_info -- HOST: fills *info (host pointer).  ADS_EINVAL on NULL. */
+ads_status ads_index_info(const ads_index *ix, ads_index_desc *info);
+
+/*
+ * ads_index_lists -- copies the list structure to caller buffers (device):
+ *   offsets [nlist + 1] int64 prefix offsets, ids [n] int64 stored ids in list
+ *   order; either pointer may be NULL.  rot_centroids [nlist][D] float32 (may be
+ *   NULL) receives the rotated centres.
+ */
+ads_status ads_index_lists(const ads_index *ix, int64_t *offsets, int64_t *ids,
+                           float *rot_centroids, hipStream_t stream);
+
+/* ads_index_free -- releases the index (synchronises the device). NULL is a no-op. */
+ads_status ads_index_free(ads_index *ix);
+
+/* --------------------------------------------------------------------------
+ * Query phase.
+ * -------------------------------------------------------------------------- */
+
+/*
+ * ads_dco_batch -- DCOs of one rotated query against explicit candidates with
+ * a fixed threshold r (Definition 2.1; Algorithm 1; the fixed-threshold
+ * protocol of Section 6.2.5).
+ *   q_rot     device [D] float32, already rotated (P q).
+ *   cand      device [m] int64 base ids; m >= 0.
+ *   r         threshold distance (not squared), >= 0, +INF allowed.
+ *   eps0      test parameter epsilon_0 >= 0 (Section 3.2); +INF never rejects.
+ *   delta_d   coordinates sampled per step, 1 <= delta_d <= D (any value; the
+ *             last step may be shorter).
+ *   method    ads_method.  PDScanning here runs on the rotated coordinates.
+ *   source    0: read the blocked list layout; 1: read the float32 row copy
+ *             (index built with keep_fp32).  Both give identical decisions for
+ *             float32 storage (the IVF+ == IVF++ property of Section 5.2).
+ *   pos_mask  device [m] uint8: 1 positive, 0 negative.
+ *   dist      device [m] float32: dis for positives, +INF for negatives.
+ *   dims      device [m] int32 coordinates sampled, or NULL.
+ *   stats     device [ADS_NSTATS] int64 accumulators, or NULL.
+ * Coordinates are summed in ascending order with one fused multiply-add per
+ * coordinate; the test at d < D is  S_d > (d/D)(1+eps0/sqrt(d))^2 r^2  (the
+ * squared form of dis' > (1+eps0/sqrt(d)) r); at d = D positive iff S_D <= r^2.
+ * Errors: ADS_EINVAL (NULL, id out of range, bad parameters), ADS_EHIP.
+ */
+ads_status ads_dco_batch(const ads_index *ix, const float *q_rot, const int64_t *cand, int64_t m,
+                         float r, float eps0, int32_t delta_d, int32_t method, int32_t source,
+                         uint8_t *pos_mask, float *dist, int32_t *dims, int64_t *stats,
+                         hipStream_t stream);
+
+/*
+ * ads_search -- IVF+ / IVF++ KNN search (Section 2.2.2 with ADSampling as the
+ * DCO, Section 4) for a batch of raw queries.
+ *   q         device [nq][D] float32 raw queries (rotated inside, end to end as
+ *             the paper measures, Section 6.1).
+ *   nq        >= 0 (0 is a no-op).
+ *   K         device [nq] int32 per-query K in [0, k_max], or NULL for k_max.
+ *   nprobe    device [nq] int32 per-query N_probe in [1, nprobe_max], or NULL
+ *             for nprobe_max.  Per-query values above nprobe_max are clamped.
+ *   k_max     >= 1; nprobe_max in [1, nlist].
+ *   eps0      >= 0, +INF selects FDScanning (no statistical test).
+ *   method    ads_method (PDScanning compares partial rotated distances).
+ *   rerank    0: plain search.  1: low-precision mode: scan with a KNN set of
+ *             4K, then recompute the 4K survivors' distances from the float32
+ *             row copy and return the best K (index built with keep_fp32).
+ *   ids       device [nq][k_max] int64, ascending by (distance, id); entries
+ *             past K[i] or past the available candidates are -1.
+ *   dist      device [nq][k_max] float32 distances; padding +INF.
+ *   probes_out device [nq][nprobe_max] int32 probed lists, nearest first
+ *             (ties to the lower list id), or NULL.  Entries past nprobe[i] are -1.
+ *   stats     device [ADS_NSTATS] int64 accumulators, or NULL.
+ *   workspace device scratch of at least ads_search_workspace_size(...) bytes,
+ *             256-byte aligned, or NULL to let the library allocate it on the
+ *             stream (stream-ordered allocation, freed on the stream).
+ * The index is read-only, so concurrent searches on different streams with
+ * different workspaces are allowed.  Each query's result depends only on that
+ * query, its K and nprobe, the index and (eps0, delta_d, method): not on the
+ * other queries of the batch.
+ */
+ads_status ads_search(const ads_index *ix, const float *q, int32_t nq, const int32_t *K,
+                      const int32_t *nprobe, int32_t k_max, int32_t nprobe_max, float eps0,
+                      int32_t method, int32_t rerank, int64_t *ids, float *dist,
+                      int32_t *probes_out, int64_t *stats, void *workspace, hipStream_t stream);
+
+/* ads_search_workspace_size -- HOST: bytes of workspace ads_search needs for
+ * these sizes (0 on invalid arguments, with ads_last_error set). */
+uint64_t ads_search_workspace_size(const ads_index *ix, int32_t nq, int32_t k_max,
+                                   int32_t nprobe_max, int32_t rerank);
+
+/* --------------------------------------------------------------------------
+ * Optional per-phase timing with HIP events (off by default).
+ * -------------------------------------------------------------------------- */
+
+enum {
+    ADS_PHASE_ROTATE = 0,   /* query rotation GEMM */
+    ADS_PHASE_PROBE = 1,    /* centre products GEMM + probe selection */
+    ADS_PHASE_GROUP = 2,    /* per-query setup and grouping of (query, list) pairs */
+    ADS_PHASE_SCAN = 3,     /* the DCO scan kernels (one launch per sweep) */
+    ADS_PHASE_MERGE = 4,    /* per-query KNN-set merges after each sweep */
+    ADS_PHASE_OUTPUT = 5,   /* output / float32 rerank */
+    ADS_NPHASES = 6
+};
+
+/*
+ * ads_profile_enable -- HOST.  on = 1: every later ads_search issued by this
+ * thread records a pair of HIP events around each phase on its stream (small
+ * overhead; not for use under stream capture).  on = 0 stops recording.
+ */
+ads_status ads_profile_enable(int32_t on);
+
+/*
+ * ads_profile_collect -- HOST.  Waits for the recorded events, adds the
+ * elapsed milliseconds of every phase into ms[ADS_NPHASES] and the number of
+ * timed launches into launches[ADS_NPHASES] (host arrays, either may be NULL),
+ * then forgets the records.
+ */
+ads_status ads_profile_collect(double *ms, int64_t *launches);
+
+/* ads_last_error -- thread-local message for the last failing call on this
+ * thread ("" if none).  The pointer stays valid until the next call. */
+const char *ads_last_error(void);
+
+/* ads_version -- library version string. */
+const char *ads_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ADS_H */

@@ -1,0 +1,13 @@
+"""MI355X-native ADSampling-IVF (Gao & Long, SIGMOD 2023).
+
+The compute path is the HIP library ``_lib/libads.so`` (sources in ``csrc/``,
+C ABI in ``include/ads.h``); this package is its ctypes binding.  PyTorch is
+used for device memory and streams only.
+"""
+
+from ._binding import (  # noqa: F401
+    ADSAMPLING, BF16, EXPORTED, F16, F32, FDSCANNING, NSTATS, PDSCANNING, STAT_BYTES, STAT_DCOS,
+    STAT_DIMS, STAT_POSITIVES, AdsError, Index, dco_batch, ivf_build, last_error, load,
+    make_rotation, profile_collect, profile_enable, rotate, search, search_workspace_size, version,
+    PHASES,
+)

@@ -1,0 +1,266 @@
+"""ctypes binding of libads.so (include/ads.h): argument marshalling only.
+
+Every step of the computation runs in the library's HIP kernels; PyTorch only
+provides device memory and the current HIP stream.  If the library is not
+built, every call raises: there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libads.so")
+
+ADS_OK, ADS_EINVAL, ADS_ENOMEM, ADS_EHIP, ADS_EUNSUPPORTED = 0, -1, -2, -3, -4
+F32, BF16, F16 = 0, 1, 2
+ADSAMPLING, FDSCANNING, PDSCANNING = 0, 1, 2
+STAT_DCOS, STAT_DIMS, STAT_POSITIVES, STAT_BYTES, NSTATS = 0, 1, 2, 3, 4
+
+EXPORTED = [
+    "ads_make_rotation", "ads_rotate", "ads_ivf_build", "ads_index_info", "ads_index_lists",
+    "ads_index_free", "ads_dco_batch", "ads_search", "ads_search_workspace_size",
+    "ads_last_error", "ads_version", "ads_profile_enable", "ads_profile_collect",
+]
+PHASES = ["rotate", "probe", "group", "scan", "merge", "output"]
+
+
+class AdsError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"ads status {status}: {message}")
+        self.status = status
+
+
+class IndexDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("D", ctypes.c_int32), ("nlist", ctypes.c_int32),
+                ("delta_d", ctypes.c_int32), ("storage", ctypes.c_int32),
+                ("has_fp32_copy", ctypes.c_int32), ("max_list", ctypes.c_int32),
+                ("device_bytes", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libads.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -m paper_2303_09855_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+    lib.ads_make_rotation.argtypes = [vp, i32, vp, vp]
+    lib.ads_rotate.argtypes = [vp, i32, vp, i64, vp, vp]
+    lib.ads_ivf_build.argtypes = [vp, i64, i32, vp, vp, i32, vp, i32, i32, i32, vp,
+                                  ctypes.POINTER(vp)]
+    lib.ads_index_info.argtypes = [vp, ctypes.POINTER(IndexDesc)]
+    lib.ads_index_lists.argtypes = [vp, vp, vp, vp, vp]
+    lib.ads_index_free.argtypes = [vp]
+    lib.ads_dco_batch.argtypes = [vp, vp, vp, i64, f32, f32, i32, i32, i32, vp, vp, vp, vp, vp]
+    lib.ads_search.argtypes = [vp, vp, i32, vp, vp, i32, i32, f32, i32, i32, vp, vp, vp, vp, vp, vp]
+    lib.ads_search_workspace_size.argtypes = [vp, i32, i32, i32, i32]
+    lib.ads_search_workspace_size.restype = ctypes.c_uint64
+    lib.ads_profile_enable.argtypes = [i32]
+    lib.ads_profile_collect.argtypes = [vp, vp]
+    lib.ads_last_error.restype = ctypes.c_char_p
+    lib.ads_version.restype = ctypes.c_char_p
+    for name in ["ads_make_rotation", "ads_rotate", "ads_ivf_build", "ads_index_info",
+                 "ads_index_lists", "ads_index_free", "ads_dco_batch", "ads_search",
+                 "ads_profile_enable", "ads_profile_collect"]:
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(st: int) -> None:
+    if st != ADS_OK:
+        raise AdsError(st, load().ads_last_error().decode())
+
+
+def last_error() -> str:
+    return load().ads_last_error().decode()
+
+
+def version() -> str:
+    return load().ads_version().decode()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev(t, dtype):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(np.ascontiguousarray(t))
+    t = t.to(device="cuda", dtype=dtype)
+    return t.contiguous()
+
+
+# ---------------------------------------------------------------------------
+# Rotation
+# ---------------------------------------------------------------------------
+
+def make_rotation(gaussian: np.ndarray):
+    """Host Householder QR of a Gaussian matrix -> (P float32, P float64)."""
+    g = np.ascontiguousarray(gaussian, dtype=np.float64)
+    D = g.shape[0]
+    if g.shape != (D, D):
+        raise ValueError("gaussian must be square")
+    P = np.empty((D, D), dtype=np.float32)
+    P64 = np.empty((D, D), dtype=np.float64)
+    _check(load().ads_make_rotation(g.ctypes.data_as(ctypes.c_void_p), D,
+                                    P.ctypes.data_as(ctypes.c_void_p),
+                                    P64.ctypes.data_as(ctypes.c_void_p)))
+    return P, P64
+
+
+def rotate(P, X):
+    """Y = X P^T on the GPU (float32 tensors)."""
+    torch = _torch()
+    P = _dev(P, torch.float32)
+    X = _dev(X, torch.float32)
+    n, D = X.shape
+    Y = torch.empty((n, D), dtype=torch.float32, device="cuda")
+    _check(load().ads_rotate(_ptr(P), D, _ptr(X), n, _ptr(Y), _stream()))
+    return Y
+
+
+# ---------------------------------------------------------------------------
+# Index
+# ---------------------------------------------------------------------------
+
+class Index:
+    """Owning handle of an ads_index."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self._h = handle
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise RuntimeError("index was freed")
+        return self._h
+
+    def info(self) -> dict:
+        d = IndexDesc()
+        _check(load().ads_index_info(self.handle, ctypes.byref(d)))
+        return {f: getattr(d, f) for f, _ in IndexDesc._fields_}
+
+    def lists(self):
+        """(offsets [nlist+1] int64, stored ids [n] int64, rotated centres) as CPU arrays."""
+        torch = _torch()
+        inf = self.info()
+        off = torch.empty(inf["nlist"] + 1, dtype=torch.int64, device="cuda")
+        ids = torch.empty(inf["n"], dtype=torch.int64, device="cuda")
+        cen = torch.empty((inf["nlist"], inf["D"]), dtype=torch.float32, device="cuda")
+        _check(load().ads_index_lists(self.handle, _ptr(off), _ptr(ids), _ptr(cen), _stream()))
+        torch.cuda.current_stream().synchronize()
+        return off.cpu().numpy(), ids.cpu().numpy(), cen.cpu().numpy()
+
+    def free(self) -> None:
+        if self._h:
+            load().ads_index_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def ivf_build(base, P, centroids, assign, delta_d: int = 32, storage: int = F32,
+              keep_fp32: bool = True) -> Index:
+    torch = _torch()
+    base = _dev(base, torch.float32)
+    P = _dev(P, torch.float32)
+    centroids = _dev(centroids, torch.float32)
+    assign = _dev(assign, torch.int32)
+    n, D = base.shape
+    out = ctypes.c_void_p()
+    _check(load().ads_ivf_build(_ptr(base), n, D, _ptr(P), _ptr(centroids), centroids.shape[0],
+                                _ptr(assign), int(delta_d), int(storage), int(bool(keep_fp32)),
+                                _stream(), ctypes.byref(out)))
+    return Index(out)
+
+
+# ---------------------------------------------------------------------------
+# Query phase
+# ---------------------------------------------------------------------------
+
+def dco_batch(index: Index, q_rot, cand, r: float, eps0: float, delta_d: int,
+              method: int = ADSAMPLING, source: int = 0, stats=None):
+    """Returns (mask uint8, dist float32, dims int32) tensors on the GPU."""
+    torch = _torch()
+    q_rot = _dev(q_rot, torch.float32).reshape(-1)
+    cand = _dev(cand, torch.int64).reshape(-1)
+    m = cand.shape[0]
+    mask = torch.empty(m, dtype=torch.uint8, device="cuda")
+    dist = torch.empty(m, dtype=torch.float32, device="cuda")
+    dims = torch.empty(m, dtype=torch.int32, device="cuda")
+    _check(load().ads_dco_batch(index.handle, _ptr(q_rot), _ptr(cand), m, float(r), float(eps0),
+                                int(delta_d), int(method), int(source), _ptr(mask), _ptr(dist),
+                                _ptr(dims), _ptr(stats), _stream()))
+    return mask, dist, dims
+
+
+def search_workspace_size(index: Index, nq: int, k_max: int, nprobe_max: int, rerank: int = 0) -> int:
+    v = load().ads_search_workspace_size(index.handle, nq, k_max, nprobe_max, rerank)
+    if v == 0:
+        raise AdsError(ADS_EINVAL, last_error())
+    return int(v)
+
+
+def search(index: Index, q, k_max: int, nprobe_max: int, eps0: float = 2.1,
+           method: int = ADSAMPLING, K=None, nprobe=None, rerank: int = 0,
+           want_probes: bool = False, stats=None, workspace=None, out=None):
+    """Batched IVF+ search.  Returns (ids int64 [nq,k_max], dist float32[, probes])."""
+    torch = _torch()
+    q = _dev(q, torch.float32)
+    nq = q.shape[0]
+    Kt = _dev(K, torch.int32) if K is not None else None
+    Nt = _dev(nprobe, torch.int32) if nprobe is not None else None
+    if out is None:
+        ids = torch.empty((nq, k_max), dtype=torch.int64, device="cuda")
+        dist = torch.empty((nq, k_max), dtype=torch.float32, device="cuda")
+    else:
+        ids, dist = out
+    probes = torch.empty((nq, nprobe_max), dtype=torch.int32, device="cuda") if want_probes else None
+    e = math.inf if eps0 is None else float(eps0)
+    _check(load().ads_search(index.handle, _ptr(q), nq, _ptr(Kt), _ptr(Nt), int(k_max),
+                             int(nprobe_max), e, int(method), int(rerank), _ptr(ids), _ptr(dist),
+                             _ptr(probes), _ptr(stats), _ptr(workspace), _stream()))
+    if want_probes:
+        return ids, dist, probes
+    return ids, dist
+
+
+# ---------------------------------------------------------------------------
+# Per-phase event timing
+# ---------------------------------------------------------------------------
+
+def profile_enable(on: bool = True) -> None:
+    _check(load().ads_profile_enable(1 if on else 0))
+
+
+def profile_collect() -> dict:
+    """{phase: (milliseconds, launches)} accumulated since the last collect."""
+    ms = np.zeros(len(PHASES), dtype=np.float64)
+    n = np.zeros(len(PHASES), dtype=np.int64)
+    _check(load().ads_profile_collect(ms.ctypes.data_as(ctypes.c_void_p), n.ctypes.data_as(ctypes.c_void_p)))
+    return {p: (float(ms[i]), int(n[i])) for i, p in enumerate(PHASES)}

@@ -1,0 +1,672 @@
+// Host side of the C ABI declared in include/ads.h: argument validation,
+// index construction, workspace layout and the launch sequence of a search.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+namespace ads {
+__global__ void setup_kernel(const int32_t *K, const int32_t *nprobe, int nq, int k_max,
+                             int nprobe_max, int kfactor, int kcap, int32_t *kq, int32_t *keff,
+                             int32_t *npq, float *r2, uint64_t *tk);
+__global__ void zero_i32_kernel(int32_t *p, int64_t n);
+__global__ void probe_select_kernel(const float *qrot, const float *dots, const float *cnorm, int D,
+                                    int nlist, int nprobe_max, int32_t *probes);
+__global__ void group_count_kernel(const int32_t *probes, const int32_t *npq, const int32_t *keff,
+                                   int nq, int nprobe_max, int nlist, int32_t *cnt);
+__global__ void group_scan_kernel(const int32_t *cnt, int nsweep, int nlist, int32_t *beg,
+                                  int32_t *unit_list, int32_t *unit_beg, int32_t *unit_cnt,
+                                  int32_t *n_units);
+__global__ void group_scatter_kernel(const int32_t *probes, const int32_t *npq, const int32_t *keff,
+                                     int nq, int nprobe_max, int nlist, const int32_t *beg,
+                                     int32_t *cursor, int2 *qent);
+__global__ void merge_kernel(const uint64_t *slots, const int32_t *keff, const int32_t *npq,
+                             int nprobe_max, int kcap, int rank_a, int rank_b, uint64_t *tk,
+                             float *r2);
+__global__ void output_kernel(const uint64_t *tk, const int32_t *kq, int nq, int k_max, int kcap,
+                              int64_t *ids, float *dist);
+__global__ void rerank_kernel(const uint64_t *tk, const int32_t *kq, const int32_t *keff,
+                              const float *rows32, const int32_t *pos_of, const float *qrot, int D,
+                              int kcap, int k_max, int64_t *ids, float *dist);
+__global__ void probes_out_kernel(const int32_t *probes, const int32_t *npq, int nq, int nprobe_max,
+                                  int32_t *out);
+}  // namespace ads
+
+using namespace ads;
+
+struct ads_index {
+    int64_t n = 0;
+    int D = 0, nlist = 0, dd = 0, nb = 0, storage = 0, keep_fp32 = 0, max_list = 0;
+    float *P = nullptr;          // [D][D]
+    float *cent_rot = nullptr;   // [nlist][D]
+    float *cent_norm = nullptr;  // [nlist]
+    int64_t *list_off = nullptr; // [nlist + 1]
+    int32_t *ids = nullptr;      // [n] stored position -> id
+    int32_t *pos_of = nullptr;   // [n] id -> stored position
+    int32_t *list_of_pos = nullptr;  // [n]
+    void *data = nullptr;        // blocked layout
+    float *rows32 = nullptr;     // [n][D] float32 rows in stored order (optional)
+    int64_t bytes = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+// Per-thread event profiler (ads_profile_enable / ads_profile_collect).
+struct Profiler {
+    bool on = false;
+    struct Rec { int phase; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get() {
+        if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    ~Profiler() {
+        for (auto &r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+thread_local Profiler g_prof;
+
+// Brackets one phase's launches with events when profiling is on.
+struct PhaseTimer {
+    hipStream_t s;
+    int phase;
+    hipEvent_t a = nullptr;
+    PhaseTimer(int ph, hipStream_t st) : s(st), phase(ph) {
+        if (g_prof.on && (a = g_prof.get())) (void)hipEventRecord(a, s);
+    }
+    ~PhaseTimer() {
+        if (!a) return;
+        hipEvent_t b = g_prof.get();
+        if (!b) { g_prof.pool.push_back(a); return; }
+        (void)hipEventRecord(b, s);
+        g_prof.recs.push_back({phase, a, b});
+    }
+};
+
+ads_status fail(ads_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+ads_status fail(ads_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+ads_status hip_fail(hipError_t e, const char *what) {
+    return fail(ADS_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                          \
+    do {                                             \
+        hipError_t e_ = (expr);                      \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+int elem_bytes(int dt) { return dt == ADS_F32 ? 4 : 2; }
+
+bool valid_dd(int dd) { return dd == 8 || dd == 16 || dd == 32 || dd == 64; }
+
+void free_index(ads_index *ix) {
+    if (!ix) return;
+    void *ptrs[] = {ix->P, ix->cent_rot, ix->cent_norm, ix->list_off, ix->ids, ix->pos_of,
+                    ix->list_of_pos, ix->data, ix->rows32};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    delete ix;
+}
+
+template <class T>
+hipError_t dmalloc(T **p, size_t count, int64_t *acc) {
+    *p = nullptr;
+    size_t bytes = count * sizeof(T);
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(p), bytes);
+    if (e == hipSuccess && acc) *acc += (int64_t)bytes;
+    return e;
+}
+
+unsigned grid_for(int64_t n, int64_t cap = 65536) {
+    int64_t g = (n + ADS_WG - 1) / ADS_WG;
+    if (g < 1) g = 1;
+    return (unsigned)(g > cap ? cap : g);
+}
+
+// Scan tile: queries per workgroup chunk for a KNN-set capacity.
+int qt_for(int kcap) {
+    if (kcap <= 64) return 32;
+    if (kcap <= 128) return 16;
+    if (kcap <= 256) return 8;
+    if (kcap <= 512) return 4;
+    return 0;
+}
+
+constexpr int KCAP_MAX = 512;
+constexpr int NPROBE_MAX_LIMIT = 8192;
+
+struct SearchLayout {
+    size_t off_qrot, off_dots, off_probes, off_kq, off_keff, off_npq, off_r2, off_tk, off_cnt,
+        off_beg, off_cursor, off_ul, off_ub, off_uc, off_nu, off_qent, off_slots, total;
+    int nsweep, kcap;
+};
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+SearchLayout layout_for(const ads_index *ix, int nq, int k_max, int nprobe_max, int rerank) {
+    SearchLayout L{};
+    L.kcap = k_max * (rerank ? 4 : 1);
+    L.nsweep = num_sweeps(nprobe_max);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align256(o + (bytes ? bytes : 1)); return at; };
+    const size_t nqs = (size_t)(nq > 0 ? nq : 1);
+    L.off_qrot = take(nqs * ix->D * sizeof(float));
+    L.off_dots = take(nqs * ix->nlist * sizeof(float));
+    L.off_probes = take(nqs * nprobe_max * sizeof(int32_t));
+    L.off_kq = take(nqs * sizeof(int32_t));
+    L.off_keff = take(nqs * sizeof(int32_t));
+    L.off_npq = take(nqs * sizeof(int32_t));
+    L.off_r2 = take(nqs * sizeof(float));
+    L.off_tk = take(nqs * L.kcap * sizeof(uint64_t));
+    const size_t sl = (size_t)L.nsweep * ix->nlist;
+    L.off_cnt = take(sl * sizeof(int32_t));
+    L.off_cursor = take(sl * sizeof(int32_t));
+    L.off_beg = take(sl * sizeof(int32_t));
+    L.off_ul = take(sl * sizeof(int32_t));
+    L.off_ub = take(sl * sizeof(int32_t));
+    L.off_uc = take(sl * sizeof(int32_t));
+    L.off_nu = take((size_t)L.nsweep * sizeof(int32_t));
+    L.off_qent = take(nqs * nprobe_max * sizeof(int2));
+    L.off_slots = take(nqs * nprobe_max * (size_t)L.kcap * sizeof(uint64_t));
+    L.total = o;
+    return L;
+}
+
+ads_status check_search_args(const ads_index *ix, int32_t nq, int32_t k_max, int32_t nprobe_max,
+                             int32_t rerank) {
+    if (!ix) return fail(ADS_EINVAL, "index is NULL");
+    if (nq < 0) return fail(ADS_EINVAL, "nq must be >= 0 (got %d)", nq);
+    if (k_max < 1) return fail(ADS_EINVAL, "k_max must be >= 1 (got %d)", k_max);
+    if (nprobe_max < 1 || nprobe_max > ix->nlist)
+        return fail(ADS_EINVAL, "nprobe_max must be in [1, nlist=%d] (got %d)", ix->nlist, nprobe_max);
+    if (nprobe_max > NPROBE_MAX_LIMIT)
+        return fail(ADS_EUNSUPPORTED, "nprobe_max above %d is not supported", NPROBE_MAX_LIMIT);
+    if (rerank != 0 && rerank != 1) return fail(ADS_EINVAL, "rerank must be 0 or 1");
+    if (rerank && !ix->rows32)
+        return fail(ADS_EINVAL, "rerank needs an index built with keep_fp32 = 1");
+    const int kcap = k_max * (rerank ? 4 : 1);
+    if (kcap > KCAP_MAX)
+        return fail(ADS_EUNSUPPORTED, "k_max%s above %d is not supported", rerank ? " * 4" : "", KCAP_MAX);
+    if ((int64_t)nq * nprobe_max >= (int64_t)1 << 31)
+        return fail(ADS_EUNSUPPORTED, "nq * nprobe_max must be below 2^31");
+    return ADS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Rotation
+// ---------------------------------------------------------------------------
+
+extern "C" ads_status ads_make_rotation(const double *gaussian, int32_t D, float *P_out, double *P64_out) {
+    if (!gaussian || !P_out) return fail(ADS_EINVAL, "gaussian and P_out must not be NULL");
+    if (D < 1) return fail(ADS_EINVAL, "D must be >= 1 (got %d)", D);
+    const size_t N = (size_t)D;
+    std::vector<double> a, v, rdiag, q;
+    try {
+        a.resize(N * N);
+        v.resize(N * N);
+        rdiag.resize(N);
+        q.assign(N * N, 0.0);
+    } catch (...) {
+        return fail(ADS_ENOMEM, "host allocation failed");
+    }
+    // column-major working copy: a[j*D + i] = G[i][j]
+    for (size_t i = 0; i < N; ++i)
+        for (size_t j = 0; j < N; ++j) a[j * N + i] = gaussian[i * N + j];
+    // Householder QR: H_k zeroes column k below the diagonal.
+    for (size_t k = 0; k < N; ++k) {
+        double *col = &a[k * N];
+        double nrm = 0.0;
+        for (size_t i = k; i < N; ++i) nrm += col[i] * col[i];
+        nrm = std::sqrt(nrm);
+        double *vk = &v[k * N];
+        for (size_t i = 0; i < N; ++i) vk[i] = 0.0;
+        if (nrm == 0.0) {
+            rdiag[k] = 0.0;
+            continue;
+        }
+        const double alpha = col[k] >= 0.0 ? -nrm : nrm;
+        for (size_t i = k; i < N; ++i) vk[i] = col[i];
+        vk[k] -= alpha;
+        double vn = 0.0;
+        for (size_t i = k; i < N; ++i) vn += vk[i] * vk[i];
+        vn = std::sqrt(vn);
+        if (vn == 0.0) {
+            rdiag[k] = col[k];
+            continue;
+        }
+        for (size_t i = k; i < N; ++i) vk[i] /= vn;
+        for (size_t j = k; j < N; ++j) {
+            double *cj = &a[j * N];
+            double dot = 0.0;
+            for (size_t i = k; i < N; ++i) dot += vk[i] * cj[i];
+            dot *= 2.0;
+            for (size_t i = k; i < N; ++i) cj[i] -= dot * vk[i];
+        }
+        rdiag[k] = a[k * N + k];
+    }
+    // Q = H_0 H_1 ... H_{D-1} applied to the identity (column-major q).
+    for (size_t j = 0; j < N; ++j) q[j * N + j] = 1.0;
+    for (size_t kk = N; kk-- > 0;) {
+        const double *vk = &v[kk * N];
+        for (size_t j = 0; j < N; ++j) {
+            double *qj = &q[j * N];
+            double dot = 0.0;
+            for (size_t i = kk; i < N; ++i) dot += vk[i] * qj[i];
+            if (dot == 0.0) continue;
+            dot *= 2.0;
+            for (size_t i = kk; i < N; ++i) qj[i] -= dot * vk[i];
+        }
+    }
+    // Haar sign fix: Q <- Q diag(sign(diag R)).
+    for (size_t j = 0; j < N; ++j) {
+        const double sgn = rdiag[j] < 0.0 ? -1.0 : 1.0;
+        for (size_t i = 0; i < N; ++i) {
+            const double val = sgn * q[j * N + i];
+            P_out[i * N + j] = (float)val;
+            if (P64_out) P64_out[i * N + j] = val;
+        }
+    }
+    return ADS_OK;
+}
+
+extern "C" ads_status ads_rotate(const float *P, int32_t D, const float *X, int64_t n, float *Y,
+                                 hipStream_t stream) {
+    if (n < 0) return fail(ADS_EINVAL, "n must be >= 0");
+    if (n == 0) return ADS_OK;
+    if (!P || !X || !Y) return fail(ADS_EINVAL, "P, X and Y must not be NULL");
+    if (D < 1 || D % 4 != 0) return fail(ADS_EINVAL, "D must be a positive multiple of 4 (got %d)", D);
+    if (X == Y) return fail(ADS_EINVAL, "X and Y must not alias");
+    HIP_TRY(hipGetLastError(), "pending HIP error");
+    HIP_TRY(gemm_nt_f32(X, D, P, D, Y, D, n, D, D, stream), "rotate");
+    return ADS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Index
+// ---------------------------------------------------------------------------
+
+extern "C" ads_status ads_ivf_build(const float *base, int64_t n, int32_t D, const float *P,
+                                    const float *centroids, int32_t nlist, const int32_t *assign,
+                                    int32_t delta_d, int32_t storage, int32_t keep_fp32,
+                                    hipStream_t stream, ads_index **out) {
+    if (!out) return fail(ADS_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    if (!base || !P || !centroids || !assign)
+        return fail(ADS_EINVAL, "base, P, centroids and assign must not be NULL");
+    if (n < 1 || n >= ((int64_t)1 << 31)) return fail(ADS_EINVAL, "n must be in [1, 2^31) (got %lld)", (long long)n);
+    if (D < 1 || D % 4 != 0) return fail(ADS_EINVAL, "D must be a positive multiple of 4 (got %d)", D);
+    if (nlist < 1) return fail(ADS_EINVAL, "nlist must be >= 1 (got %d)", nlist);
+    if (storage != ADS_F32 && storage != ADS_BF16 && storage != ADS_F16)
+        return fail(ADS_EINVAL, "unknown storage type %d", storage);
+    if (!valid_dd(delta_d))
+        return fail(ADS_EUNSUPPORTED, "delta_d must be one of 8, 16, 32, 64 (got %d)", delta_d);
+    if (D % delta_d != 0) return fail(ADS_EINVAL, "delta_d=%d must divide D=%d", delta_d, D);
+    if (storage != ADS_F32 && D % 8 != 0) return fail(ADS_EINVAL, "16-bit storage needs D %% 8 == 0");
+    if (keep_fp32 != 0 && keep_fp32 != 1) return fail(ADS_EINVAL, "keep_fp32 must be 0 or 1");
+    HIP_TRY(hipGetLastError(), "pending HIP error");
+
+    std::vector<int32_t> h_assign;
+    try {
+        h_assign.resize((size_t)n);
+    } catch (...) {
+        return fail(ADS_ENOMEM, "host allocation failed");
+    }
+    HIP_TRY(hipMemcpyAsync(h_assign.data(), assign, sizeof(int32_t) * n, hipMemcpyDeviceToHost, stream),
+            "copy assign");
+    HIP_TRY(hipStreamSynchronize(stream), "synchronize");
+    std::vector<int64_t> off((size_t)nlist + 1, 0);
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t l = h_assign[(size_t)i];
+        if (l < 0 || l >= nlist) return fail(ADS_EINVAL, "assign[%lld] = %d is outside [0, %d)", (long long)i, l, nlist);
+        off[(size_t)l + 1]++;
+    }
+    int max_list = 0;
+    for (int l = 0; l < nlist; ++l) {
+        if (off[(size_t)l + 1] > max_list) max_list = (int)off[(size_t)l + 1];
+        off[(size_t)l + 1] += off[(size_t)l];
+    }
+    // stable counting sort: ascending id inside every list
+    std::vector<int32_t> ids((size_t)n), pos_of((size_t)n), lop((size_t)n);
+    {
+        std::vector<int64_t> cur(off.begin(), off.end() - 1);
+        for (int64_t i = 0; i < n; ++i) {
+            int32_t l = h_assign[(size_t)i];
+            int64_t p = cur[(size_t)l]++;
+            ids[(size_t)p] = (int32_t)i;
+            pos_of[(size_t)i] = (int32_t)p;
+            lop[(size_t)p] = l;
+        }
+    }
+
+    ads_index *ix = new (std::nothrow) ads_index();
+    if (!ix) return fail(ADS_ENOMEM, "host allocation failed");
+    ix->n = n;
+    ix->D = D;
+    ix->nlist = nlist;
+    ix->dd = delta_d;
+    ix->nb = D / delta_d;
+    ix->storage = storage;
+    ix->keep_fp32 = keep_fp32;
+    ix->max_list = max_list;
+    float *rot = nullptr;
+    hipError_t e = hipSuccess;
+#define BUILD_TRY(expr, what)          \
+    do {                               \
+        e = (expr);                    \
+        if (e != hipSuccess) {         \
+            ads_status st = hip_fail(e, what); \
+            if (rot) (void)hipFree(rot); \
+            (void)hipStreamSynchronize(stream); \
+            free_index(ix);            \
+            if (e == hipErrorOutOfMemory) st = fail(ADS_ENOMEM, "%s: out of device memory", what); \
+            return st;                 \
+        }                              \
+    } while (0)
+    BUILD_TRY(dmalloc(&ix->P, (size_t)D * D, &ix->bytes), "alloc P");
+    BUILD_TRY(dmalloc(&ix->cent_rot, (size_t)nlist * D, &ix->bytes), "alloc centroids");
+    BUILD_TRY(dmalloc(&ix->cent_norm, (size_t)nlist, &ix->bytes), "alloc centroid norms");
+    BUILD_TRY(dmalloc(&ix->list_off, (size_t)nlist + 1, &ix->bytes), "alloc offsets");
+    BUILD_TRY(dmalloc(&ix->ids, (size_t)n, &ix->bytes), "alloc ids");
+    BUILD_TRY(dmalloc(&ix->pos_of, (size_t)n, &ix->bytes), "alloc positions");
+    BUILD_TRY(dmalloc(&ix->list_of_pos, (size_t)n, &ix->bytes), "alloc list of position");
+    {
+        const size_t data_bytes = (size_t)n * D * elem_bytes(storage);
+        e = hipMalloc(&ix->data, data_bytes);
+        if (e == hipSuccess) ix->bytes += (int64_t)data_bytes;
+        BUILD_TRY(e, "alloc blocked layout");
+    }
+    if (keep_fp32) BUILD_TRY(dmalloc(&ix->rows32, (size_t)n * D, &ix->bytes), "alloc float32 rows");
+    BUILD_TRY(hipMalloc(&rot, sizeof(float) * (size_t)n * D), "alloc rotation scratch");
+
+    BUILD_TRY(hipMemcpyAsync(ix->P, P, sizeof(float) * D * D, hipMemcpyDeviceToDevice, stream), "copy P");
+    BUILD_TRY(hipMemcpyAsync(ix->list_off, off.data(), sizeof(int64_t) * (nlist + 1), hipMemcpyHostToDevice, stream), "upload offsets");
+    BUILD_TRY(hipMemcpyAsync(ix->ids, ids.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream), "upload ids");
+    BUILD_TRY(hipMemcpyAsync(ix->pos_of, pos_of.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream), "upload positions");
+    BUILD_TRY(hipMemcpyAsync(ix->list_of_pos, lop.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream), "upload list ids");
+    // rotate every base vector (index phase, Section 6.1) and pack the lists
+    BUILD_TRY(gemm_nt_f32(base, D, ix->P, D, rot, D, n, D, D, stream), "rotate base");
+    BUILD_TRY(launch_pack(storage, rot, ix->ids, ix->list_of_pos, ix->list_off, n, D, delta_d, ix->data,
+                          ix->rows32, stream), "pack lists");
+    BUILD_TRY(gemm_nt_f32(centroids, D, ix->P, D, ix->cent_rot, D, nlist, D, D, stream), "rotate centroids");
+    BUILD_TRY(launch_row_norms(ix->cent_rot, nlist, D, ix->cent_norm, stream), "centroid norms");
+    BUILD_TRY(hipStreamSynchronize(stream), "synchronize build");
+    (void)hipFree(rot);
+    rot = nullptr;
+#undef BUILD_TRY
+    *out = ix;
+    return ADS_OK;
+}
+
+extern "C" ads_status ads_index_info(const ads_index *ix, ads_index_desc *info) {
+    if (!ix || !info) return fail(ADS_EINVAL, "index and info must not be NULL");
+    info->n = ix->n;
+    info->D = ix->D;
+    info->nlist = ix->nlist;
+    info->delta_d = ix->dd;
+    info->storage = ix->storage;
+    info->has_fp32_copy = ix->rows32 != nullptr;
+    info->max_list = ix->max_list;
+    info->device_bytes = ix->bytes;
+    return ADS_OK;
+}
+
+namespace {
+__global__ void ids_to_i64_kernel(const int32_t *in, int64_t n, int64_t *out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = in[i];
+}
+}  // namespace
+
+extern "C" ads_status ads_index_lists(const ads_index *ix, int64_t *offsets, int64_t *ids,
+                                      float *rot_centroids, hipStream_t stream) {
+    if (!ix) return fail(ADS_EINVAL, "index is NULL");
+    HIP_TRY(hipGetLastError(), "pending HIP error");
+    if (offsets)
+        HIP_TRY(hipMemcpyAsync(offsets, ix->list_off, sizeof(int64_t) * (ix->nlist + 1), hipMemcpyDeviceToDevice, stream),
+                "copy offsets");
+    if (ids) {
+        hipLaunchKernelGGL(ids_to_i64_kernel, dim3(grid_for(ix->n)), dim3(ADS_WG), 0, stream, ix->ids, ix->n, ids);
+        HIP_TRY(hipGetLastError(), "copy ids");
+    }
+    if (rot_centroids)
+        HIP_TRY(hipMemcpyAsync(rot_centroids, ix->cent_rot, sizeof(float) * ix->nlist * ix->D, hipMemcpyDeviceToDevice, stream),
+                "copy centroids");
+    return ADS_OK;
+}
+
+extern "C" ads_status ads_index_free(ads_index *ix) {
+    if (!ix) return ADS_OK;
+    (void)hipDeviceSynchronize();
+    free_index(ix);
+    return ADS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Query phase
+// ---------------------------------------------------------------------------
+
+extern "C" ads_status ads_dco_batch(const ads_index *ix, const float *q_rot, const int64_t *cand, int64_t m,
+                                    float r, float eps0, int32_t delta_d, int32_t method, int32_t source,
+                                    uint8_t *pos_mask, float *dist, int32_t *dims, int64_t *stats,
+                                    hipStream_t stream) {
+    if (!ix) return fail(ADS_EINVAL, "index is NULL");
+    if (m < 0) return fail(ADS_EINVAL, "m must be >= 0");
+    if (m == 0) return ADS_OK;
+    if (!q_rot || !cand || !pos_mask || !dist) return fail(ADS_EINVAL, "q_rot, cand, pos_mask and dist must not be NULL");
+    if (!(r >= 0.f)) return fail(ADS_EINVAL, "r must be >= 0 (got %g)", (double)r);
+    if (!(eps0 >= 0.f)) return fail(ADS_EINVAL, "eps0 must be >= 0 (got %g)", (double)eps0);
+    if (delta_d < 1 || delta_d > ix->D) return fail(ADS_EINVAL, "delta_d must be in [1, D=%d] (got %d)", ix->D, delta_d);
+    if (method < 0 || method > 2) return fail(ADS_EINVAL, "unknown method %d", method);
+    if (source != 0 && source != 1) return fail(ADS_EINVAL, "source must be 0 or 1");
+    if (source == 1 && !ix->rows32) return fail(ADS_EINVAL, "source 1 needs an index built with keep_fp32 = 1");
+    HIP_TRY(hipGetLastError(), "pending HIP error");
+    const float r2 = r * r;
+    HIP_TRY(launch_dco(ix->storage, ix->data, ix->rows32, source, ix->list_off, ix->list_of_pos, ix->pos_of,
+                       ix->n, ix->D, ix->dd, q_rot, cand, m, r2, (double)eps0, delta_d, method, pos_mask,
+                       dist, dims, reinterpret_cast<unsigned long long *>(stats), stream),
+            "dco_batch");
+    return ADS_OK;
+}
+
+extern "C" uint64_t ads_search_workspace_size(const ads_index *ix, int32_t nq, int32_t k_max,
+                                              int32_t nprobe_max, int32_t rerank) {
+    if (check_search_args(ix, nq, k_max, nprobe_max, rerank) != ADS_OK) return 0;
+    return (uint64_t)layout_for(ix, nq, k_max, nprobe_max, rerank).total;
+}
+
+extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq, const int32_t *K,
+                                 const int32_t *nprobe, int32_t k_max, int32_t nprobe_max, float eps0,
+                                 int32_t method, int32_t rerank, int64_t *ids, float *dist,
+                                 int32_t *probes_out, int64_t *stats, void *workspace, hipStream_t stream) {
+    ads_status st = check_search_args(ix, nq, k_max, nprobe_max, rerank);
+    if (st != ADS_OK) return st;
+    if (nq == 0) return ADS_OK;
+    if (!q || !ids || !dist) return fail(ADS_EINVAL, "q, ids and dist must not be NULL");
+    if (!(eps0 >= 0.f)) return fail(ADS_EINVAL, "eps0 must be >= 0 (got %g)", (double)eps0);
+    if (method < 0 || method > 2) return fail(ADS_EINVAL, "unknown method %d", method);
+    if (workspace && (reinterpret_cast<uintptr_t>(workspace) & 255u))
+        return fail(ADS_EINVAL, "workspace must be 256-byte aligned");
+    HIP_TRY(hipGetLastError(), "pending HIP error");
+
+    const SearchLayout L = layout_for(ix, nq, k_max, nprobe_max, rerank);
+    const int qt = qt_for(L.kcap);
+    const int D = ix->D, nlist = ix->nlist;
+    const int eff_method = std::isinf(eps0) && method == ADS_METHOD_ADSAMPLING ? ADS_METHOD_FDSCANNING : method;
+    unsigned char *ws = reinterpret_cast<unsigned char *>(workspace);
+    bool own = false;
+    if (!ws) {
+        hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&ws), L.total, stream);
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(ADS_ENOMEM, "workspace: out of device memory")
+                                                             : hip_fail(e, "workspace allocation");
+        own = true;
+    }
+    float *qrot = reinterpret_cast<float *>(ws + L.off_qrot);
+    float *dots = reinterpret_cast<float *>(ws + L.off_dots);
+    int32_t *probes = reinterpret_cast<int32_t *>(ws + L.off_probes);
+    int32_t *kq = reinterpret_cast<int32_t *>(ws + L.off_kq);
+    int32_t *keff = reinterpret_cast<int32_t *>(ws + L.off_keff);
+    int32_t *npq = reinterpret_cast<int32_t *>(ws + L.off_npq);
+    float *r2 = reinterpret_cast<float *>(ws + L.off_r2);
+    uint64_t *tk = reinterpret_cast<uint64_t *>(ws + L.off_tk);
+    int32_t *cnt = reinterpret_cast<int32_t *>(ws + L.off_cnt);
+    int32_t *cursor = reinterpret_cast<int32_t *>(ws + L.off_cursor);
+    int32_t *beg = reinterpret_cast<int32_t *>(ws + L.off_beg);
+    int32_t *ul = reinterpret_cast<int32_t *>(ws + L.off_ul);
+    int32_t *ub = reinterpret_cast<int32_t *>(ws + L.off_ub);
+    int32_t *uc = reinterpret_cast<int32_t *>(ws + L.off_uc);
+    int32_t *nu = reinterpret_cast<int32_t *>(ws + L.off_nu);
+    int2 *qent = reinterpret_cast<int2 *>(ws + L.off_qent);
+    uint64_t *slots = reinterpret_cast<uint64_t *>(ws + L.off_slots);
+
+    hipError_t e = hipSuccess;
+    auto done = [&](hipError_t err, const char *what) -> ads_status {
+        if (own) (void)hipFreeAsync(ws, stream);
+        return err == hipSuccess ? ADS_OK : hip_fail(err, what);
+    };
+#define SEARCH_TRY(expr, what)               \
+    do {                                     \
+        e = (expr);                          \
+        if (e != hipSuccess) return done(e, what); \
+    } while (0)
+
+    const int sl = L.nsweep * nlist;
+    {
+        PhaseTimer t(ADS_PHASE_GROUP, stream);
+        hipLaunchKernelGGL(setup_kernel, dim3(grid_for((int64_t)nq * L.kcap)), dim3(ADS_WG), 0, stream, K, nprobe,
+                           nq, k_max, nprobe_max, rerank ? 4 : 1, L.kcap, kq, keff, npq, r2, tk);
+        SEARCH_TRY(hipGetLastError(), "setup");
+        hipLaunchKernelGGL(zero_i32_kernel, dim3(grid_for(sl)), dim3(ADS_WG), 0, stream, cnt, (int64_t)sl);
+        hipLaunchKernelGGL(zero_i32_kernel, dim3(grid_for(sl)), dim3(ADS_WG), 0, stream, cursor, (int64_t)sl);
+        SEARCH_TRY(hipGetLastError(), "zero counters");
+    }
+    // 1. query rotation (Section 3.1) and centre inner products (MFMA)
+    {
+        PhaseTimer t(ADS_PHASE_ROTATE, stream);
+        SEARCH_TRY(gemm_nt_f32(q, D, ix->P, D, qrot, D, nq, D, D, stream), "rotate queries");
+    }
+    // 2. probe selection
+    {
+        PhaseTimer t(ADS_PHASE_PROBE, stream);
+        SEARCH_TRY(gemm_nt_f32(qrot, D, ix->cent_rot, D, dots, nlist, nq, nlist, D, stream), "centre products");
+        const size_t sh = sizeof(uint64_t) * (size_t)next_pow2(nprobe_max);
+        hipLaunchKernelGGL(probe_select_kernel, dim3(nq), dim3(ADS_WG), sh, stream, qrot, dots, ix->cent_norm, D,
+                           nlist, nprobe_max, probes);
+        SEARCH_TRY(hipGetLastError(), "probe selection");
+    }
+    // 3. group (query, rank) pairs by (sweep, list)
+    {
+        PhaseTimer t(ADS_PHASE_GROUP, stream);
+        hipLaunchKernelGGL(group_count_kernel, dim3(grid_for((int64_t)nq * nprobe_max)), dim3(ADS_WG), 0, stream,
+                           probes, npq, keff, nq, nprobe_max, nlist, cnt);
+        hipLaunchKernelGGL(group_scan_kernel, dim3(1), dim3(1024), 0, stream, cnt, L.nsweep, nlist, beg, ul, ub, uc,
+                           nu);
+        hipLaunchKernelGGL(group_scatter_kernel, dim3(grid_for((int64_t)nq * nprobe_max)), dim3(ADS_WG), 0, stream,
+                           probes, npq, keff, nq, nprobe_max, nlist, beg, cursor, qent);
+        SEARCH_TRY(hipGetLastError(), "grouping");
+    }
+    // 4. sweeps: list-major scan, then per-query merge
+    for (int s = 0; s < L.nsweep; ++s) {
+        const int ra = sweep_begin(s);
+        int rb = s + 1 < L.nsweep ? sweep_begin(s + 1) : nprobe_max;
+        if (rb > nprobe_max) rb = nprobe_max;
+        ScanArgs a;
+        a.data = ix->data;
+        a.list_off = ix->list_off;
+        a.ids = ix->ids;
+        a.qrot = qrot;
+        a.keff = keff;
+        a.r2_in = r2;
+        a.unit_list = ul + (size_t)s * nlist;
+        a.unit_beg = ub + (size_t)s * nlist;
+        a.unit_cnt = uc + (size_t)s * nlist;
+        a.n_units = nu + s;
+        a.qent = qent;
+        a.slots = slots;
+        a.stats = reinterpret_cast<unsigned long long *>(stats);
+        a.eps0 = (double)eps0;
+        a.method = eff_method;
+        a.nprobe_max = nprobe_max;
+        a.kcap = L.kcap;
+        a.D = D;
+        a.nb = ix->nb;
+        int64_t units_bound = (int64_t)nq * (rb - ra);
+        const int grid = (int)(units_bound < nlist ? units_bound : nlist);
+        {
+            PhaseTimer t(ADS_PHASE_SCAN, stream);
+            SEARCH_TRY(launch_scan(a, ix->storage, ix->dd, qt, grid, stream), "scan");
+        }
+        const size_t sh = sizeof(uint64_t) * (size_t)next_pow2(L.kcap);
+        PhaseTimer tm(ADS_PHASE_MERGE, stream);
+        hipLaunchKernelGGL(merge_kernel, dim3(nq), dim3(ADS_WG), sh, stream, slots, keff, npq, nprobe_max, L.kcap,
+                           ra, rb, tk, r2);
+        SEARCH_TRY(hipGetLastError(), "merge");
+    }
+    // 5. output (or float32 rerank of the 4K survivors)
+    {
+        PhaseTimer t(ADS_PHASE_OUTPUT, stream);
+        if (rerank) {
+            const size_t sh = sizeof(uint64_t) * (size_t)next_pow2(L.kcap);
+            hipLaunchKernelGGL(rerank_kernel, dim3(nq), dim3(ADS_WG), sh, stream, tk, kq, keff, ix->rows32,
+                               ix->pos_of, qrot, D, L.kcap, k_max, ids, dist);
+        } else {
+            hipLaunchKernelGGL(output_kernel, dim3(grid_for((int64_t)nq * k_max)), dim3(ADS_WG), 0, stream, tk, kq,
+                               nq, k_max, L.kcap, ids, dist);
+        }
+        SEARCH_TRY(hipGetLastError(), "output");
+    }
+    if (probes_out) {
+        hipLaunchKernelGGL(probes_out_kernel, dim3(grid_for((int64_t)nq * nprobe_max)), dim3(ADS_WG), 0, stream,
+                           probes, npq, nq, nprobe_max, probes_out);
+        SEARCH_TRY(hipGetLastError(), "probes output");
+    }
+#undef SEARCH_TRY
+    return done(hipSuccess, "");
+}
+
+extern "C" ads_status ads_profile_enable(int32_t on) {
+    g_prof.on = on != 0;
+    return ADS_OK;
+}
+
+extern "C" ads_status ads_profile_collect(double *ms, int64_t *launches) {
+    ads_status st = ADS_OK;
+    for (auto &r : g_prof.recs) {
+        float t = 0.f;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+        if (e != hipSuccess && st == ADS_OK) st = hip_fail(e, "profile events");
+        if (ms && r.phase >= 0 && r.phase < ADS_NPHASES) ms[r.phase] += (double)t;
+        if (launches && r.phase >= 0 && r.phase < ADS_NPHASES) launches[r.phase] += 1;
+        g_prof.pool.push_back(r.a);
+        g_prof.pool.push_back(r.b);
+    }
+    g_prof.recs.clear();
+    return st;
+}
+
+extern "C" const char *ads_last_error(void) { return g_err.c_str(); }
+
+extern "C" const char *ads_version(void) { return "ads-mi355x 0.1.0 (gfx950)"; }

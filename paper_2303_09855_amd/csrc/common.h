@@ -1,0 +1,166 @@
+// Internal helpers shared by the library's HIP sources (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include "../../include/ads.h"
+
+#define ADS_WG 256          // threads per workgroup for every kernel here
+#define ADS_WAVE 64
+
+namespace ads {
+
+// ---------------------------------------------------------------------------
+// Keys: (squared distance, id) packed into one uint64 so that unsigned order is
+// lexicographic order.  A non-negative float orders like its bit pattern.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t make_key(float s, uint32_t id) {
+    return ((uint64_t)__float_as_uint(s) << 32) | (uint64_t)id;
+}
+__device__ __forceinline__ float key_dist2(uint64_t k) { return __uint_as_float((uint32_t)(k >> 32)); }
+__device__ __forceinline__ uint32_t key_id(uint64_t k) { return (uint32_t)k; }
+constexpr uint64_t KEY_NONE = ~0ull;
+
+// ---------------------------------------------------------------------------
+// Test coefficients.  For a DCO that has sampled d of D coordinates with
+// partial sum S_d, ADSampling rejects dis <= r when
+//     sqrt(D/d * S_d) > (1 + eps0/sqrt(d)) * r
+// (Section 3.2), i.e. S_d > coef(d) * r^2 with coef(d) = (d/D)(1+eps0/sqrt(d))^2.
+// PDScanning rejects when S_d > r^2 (coef = 1).  FDScanning never tests (+inf).
+// Computed in double on the device by every kernel, so the scan and the
+// explicit-candidate DCO use bit-identical thresholds.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float test_coef(int d, int D, double eps0, int method) {
+    if (method == ADS_METHOD_FDSCANNING) return __builtin_inff();
+    if (method == ADS_METHOD_PDSCANNING) return 1.0f;
+    if (__builtin_isinf(eps0)) return __builtin_inff();
+    double g = 1.0 + eps0 / __builtin_sqrt((double)d);
+    return (float)(((double)d / (double)D) * g * g);
+}
+
+// S > coef * r2 with the conventions: coef = +inf never rejects (also when
+// r2 == 0, where inf * 0 would be NaN), r2 = +inf never rejects.
+__device__ __forceinline__ bool test_reject(float s, float coef, float r2) {
+    if (__builtin_isinf(coef)) return false;
+    return s > coef * r2;
+}
+
+// ---------------------------------------------------------------------------
+// Storage element loads (8 consecutive elements, converted to float).
+// ---------------------------------------------------------------------------
+template <int DT> struct Elem;
+template <> struct Elem<ADS_F32> { typedef float T; static constexpr int bytes = 4; };
+template <> struct Elem<ADS_BF16> { typedef uint16_t T; static constexpr int bytes = 2; };
+template <> struct Elem<ADS_F16> { typedef uint16_t T; static constexpr int bytes = 2; };
+
+__device__ __forceinline__ float bf16_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
+__device__ __forceinline__ float f16_to_f32(uint32_t h) {
+    return __half2float(__ushort_as_half((unsigned short)h));
+}
+
+// Loads N (multiple of 4 for f32, of 8 for 16-bit) contiguous elements starting
+// at p (aligned to 16 bytes) into out[0..N).
+template <int DT, int N>
+__device__ __forceinline__ void load_elems(const void *p, float *out) {
+    if constexpr (DT == ADS_F32) {
+        const float4 *v = reinterpret_cast<const float4 *>(p);
+#pragma unroll
+        for (int i = 0; i < N / 4; ++i) {
+            float4 t = v[i];
+            out[4 * i + 0] = t.x; out[4 * i + 1] = t.y; out[4 * i + 2] = t.z; out[4 * i + 3] = t.w;
+        }
+    } else {
+        const uint4 *v = reinterpret_cast<const uint4 *>(p);
+#pragma unroll
+        for (int i = 0; i < N / 8; ++i) {
+            uint4 t = v[i];
+            uint32_t w[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if constexpr (DT == ADS_BF16) {
+                    out[8 * i + 2 * j + 0] = bf16_to_f32(w[j] & 0xffffu);
+                    out[8 * i + 2 * j + 1] = bf16_to_f32(w[j] >> 16);
+                } else {
+                    out[8 * i + 2 * j + 0] = f16_to_f32(w[j] & 0xffffu);
+                    out[8 * i + 2 * j + 1] = f16_to_f32(w[j] >> 16);
+                }
+            }
+        }
+    }
+}
+
+// One element of storage type DT at index i.
+template <int DT>
+__device__ __forceinline__ float load_one(const void *p, int64_t i) {
+    if constexpr (DT == ADS_F32) return reinterpret_cast<const float *>(p)[i];
+    else if constexpr (DT == ADS_BF16) return bf16_to_f32(reinterpret_cast<const uint16_t *>(p)[i]);
+    else return f16_to_f32(reinterpret_cast<const uint16_t *>(p)[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup-wide bitonic sort of n (power of two) uint64 keys in LDS, ascending.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void lds_bitonic_sort(uint64_t *buf, int n) {
+    for (int k = 2; k <= n; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                int ixj = i ^ j;
+                if (ixj > i) {
+                    uint64_t a = buf[i], b = buf[ixj];
+                    bool up = (i & k) == 0;
+                    if ((a > b) == up) { buf[i] = b; buf[ixj] = a; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup radix select: the k-th smallest (1-based) of n uint64 keys produced
+// by get(i), 8 passes of 8 bits from the most significant byte.
+// hist: LDS [256] uint32; misc: LDS [2] uint32.  All threads return the key.
+// Requires 1 <= k <= n.
+// ---------------------------------------------------------------------------
+template <class Get>
+__device__ uint64_t radix_kth(Get get, int n, int k, uint32_t *hist, uint32_t *misc) {
+    uint64_t prefix = 0, pmask = 0;
+    uint32_t kk = (uint32_t)k;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        hist[threadIdx.x] = 0;
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            uint64_t key = get(i);
+            if ((key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t acc = 0, sel = 255;
+            for (uint32_t d = 0; d < 256; ++d) {
+                uint32_t h = hist[d];
+                if (acc + h >= kk) { sel = d; break; }
+                acc += h;
+            }
+            misc[0] = sel;
+            misc[1] = kk - acc;
+        }
+        __syncthreads();
+        uint32_t sel = misc[0];
+        kk = misc[1];
+        prefix |= (uint64_t)sel << shift;
+        pmask |= (uint64_t)0xff << shift;
+        __syncthreads();
+    }
+    return prefix;
+}
+
+__host__ __device__ inline int next_pow2(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+}  // namespace ads

@@ -1,0 +1,46 @@
+// Launchers and kernels shared between the library's HIP sources.
+#pragma once
+#include "common.h"
+
+namespace ads {
+
+hipError_t gemm_nt_f32(const float *A, int64_t lda, const float *B, int64_t ldb, float *C,
+                       int64_t ldc, int64_t M, int64_t N, int K, hipStream_t s);
+
+struct ScanArgs {
+    const void *data;
+    const int64_t *list_off;
+    const int32_t *ids;
+    const float *qrot;
+    const int32_t *keff;
+    const float *r2_in;
+    const int32_t *unit_list;
+    const int32_t *unit_beg;
+    const int32_t *unit_cnt;
+    const int32_t *n_units;
+    const int2 *qent;
+    uint64_t *slots;
+    unsigned long long *stats;
+    double eps0;
+    int method;
+    int nprobe_max, kcap, D, nb;
+};
+
+hipError_t launch_scan(const ScanArgs &a, int dtype, int dd, int qt, int grid, hipStream_t s);
+
+int num_sweeps(int nprobe_max);
+int sweep_begin(int s);
+
+hipError_t launch_dco(int dtype, const void *data, const float *rows32, int source,
+                      const int64_t *list_off, const int32_t *list_of_pos, const int32_t *pos_of,
+                      int64_t n, int D, int dd_layout, const float *q, const int64_t *cand,
+                      int64_t m, float r2, double eps0, int step, int method, uint8_t *mask,
+                      float *dist, int32_t *dims, unsigned long long *stats, hipStream_t s);
+
+hipError_t launch_pack(int dtype, const float *rot, const int32_t *ids, const int32_t *list_of_pos,
+                       const int64_t *list_off, int64_t n, int D, int dd, void *data,
+                       float *rows32, hipStream_t s);
+
+hipError_t launch_row_norms(const float *x, int64_t n, int D, float *out, hipStream_t s);
+
+}  // namespace ads

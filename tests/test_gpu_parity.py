@@ -1,0 +1,247 @@
+"""GPU parity: the HIP library against the FP64 oracle on the same seeded
+inputs, through the C ABI.  Tolerances: decisions may differ only inside the
+1e-5 relative band around a test boundary; distances within 1e-5 relative of
+the FP64 values; ids equal at eps0 = +inf outside the tie band; recall@K
+within 0.002 of the oracle's."""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import Workload, tie_band_equal
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ads():
+    import paper_2303_09855_amd as m
+    m.load()
+    assert torch.cuda.is_available(), "the GPU tests need a visible GPU"
+    return m
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+# ---------------------------------------------------------------------------
+# Section 3.1: rotation on the matrix cores
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("model,n,D", [("mix", 1000, 128), ("lowrank", 300, 960), ("mix", 77, 256)])
+def test_rotate_matches_oracle(ads, model, n, D):
+    w = Workload(model, n, 4, D, 1, 11)
+    P32, _ = ads.make_rotation(w.G)
+    Y = _np(ads.rotate(P32, w.x))
+    err = np.linalg.norm(Y - w.xr, axis=1) / np.linalg.norm(w.x, axis=1)
+    # fp32 P (2^-24 per entry) plus fp32 accumulation: worst case ~ sqrt(D) * 2^-24
+    assert err.max() < math.sqrt(D) * 2.0 ** -24 * 4
+    assert err.mean() < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# Definition 2.1 / Algorithm 1 with a fixed threshold (Section 6.2.5 protocol)
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def flat(ads):
+    w = Workload("mix", 10_000, 24, 128, 1, 1002)
+    P32, _ = ads.make_rotation(w.G)
+    ix = ads.ivf_build(w.x, P32, w.cent, w.assign, delta_d=32, storage=ads.F32, keep_fp32=True)
+    qr_gpu = ads.rotate(P32, w.q)
+    _, gt = w.gt(10)
+    return w, ix, qr_gpu, gt
+
+
+@pytest.mark.parametrize("eps0,step,method", [(2.1, 32, 0), (1.0, 32, 0), (2.1, 1, 0), (0.5, 8, 0),
+                                              (math.inf, 32, 1), (math.inf, 16, 2)])
+def test_dco_batch_matches_oracle(ads, flat, eps0, step, method):
+    w, ix, qr_gpu, gt = flat
+    cand = np.arange(w.n, dtype=np.int64)
+    checked = mism = 0
+    for qi in range(0, w.nq, 3):
+        r = float(gt[qi, 9])
+        mask, dist, dims = ads.dco_batch(ix, qr_gpu[qi], cand, r, eps0, step, method=method)
+        mask, dist, dims = _np(mask), _np(dist), _np(dims)
+        ref = oracle.dco_batch(w.xr, w.qr[qi], cand, r, eps0, step, method=method)
+        diff = mask != ref["mask"]
+        assert np.all(ref["band"][diff] == 1), f"query {qi}: mask mismatch outside the band"
+        mism += int(diff.sum())
+        same = ~diff & (ref["band"] == 0)
+        assert np.array_equal(dims[same], ref["dims"][same])
+        pos = (mask == 1) & (ref["mask"] == 1)
+        rel = np.abs(dist[pos] - ref["dist"][pos]) / ref["dist"][pos]
+        assert rel.max(initial=0) <= 1e-5
+        assert np.all(np.isinf(dist[mask == 0]))
+        checked += w.n
+    assert mism <= checked * 1e-3
+
+
+def test_dco_sources_identical(ads, flat):
+    """IVF+ and IVF++ give the same result (Section 5.2): reading the blocked
+    layout or the float32 rows yields bit-identical decisions and distances."""
+    w, ix, qr_gpu, gt = flat
+    cand = torch.randint(0, w.n, (5000,), generator=torch.Generator().manual_seed(3))
+    for qi in (0, 5):
+        a = [_np(t) for t in ads.dco_batch(ix, qr_gpu[qi], cand, float(gt[qi, 9]), 2.1, 32, source=0)]
+        b = [_np(t) for t in ads.dco_batch(ix, qr_gpu[qi], cand, float(gt[qi, 9]), 2.1, 32, source=1)]
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
+def test_dco_no_false_positives(ads, flat):
+    """Lemma 3.2: a negative object is never reported positive (up to the
+    float32 band at r itself)."""
+    w, ix, qr_gpu, gt = flat
+    cand = np.arange(w.n, dtype=np.int64)
+    for qi in (1, 2):
+        r = float(gt[qi, 9]) * 1.3
+        mask, _, _ = ads.dco_batch(ix, qr_gpu[qi], cand, r, 0.5, 8)
+        raw = oracle.exact_dist(w.x, w.q[qi])
+        assert np.all(raw[_np(mask) == 1] <= r * (1 + 1e-5))
+
+
+# ---------------------------------------------------------------------------
+# IVF search (Section 2.2.2 + Section 4)
+# ---------------------------------------------------------------------------
+
+def _build(ads, w, dd=32, storage=0):
+    P32, _ = ads.make_rotation(w.G)
+    return ads.ivf_build(w.x, P32, w.cent, w.assign, delta_d=dd, storage=storage, keep_fp32=True)
+
+
+@pytest.fixture(scope="module")
+def ivf128(ads):
+    w = Workload("mix", 30_000, 64, 128, 64, 2002)
+    return w, _build(ads, w)
+
+
+@pytest.fixture(scope="module")
+def ivf960(ads):
+    w = Workload("lowrank", 20_000, 40, 960, 48, 3002)
+    return w, _build(ads, w)
+
+
+def _check_probes(w, probes_gpu, nprobe):
+    pr, d2 = w.oracle_probes(nprobe)
+    bad = 0
+    for i in range(w.nq):
+        if list(probes_gpu[i]) == list(pr[i]):
+            continue
+        kth = d2[i][pr[i][-1]]
+        band = np.abs(d2[i] - kth) <= 1e-4 * kth
+        assert set(probes_gpu[i][~np.isin(probes_gpu[i], np.flatnonzero(band))]) == \
+            set(pr[i][~np.isin(pr[i], np.flatnonzero(band))])
+        bad += 1
+    return pr, bad
+
+
+@pytest.mark.parametrize("fixture,nprobe,K", [("ivf128", 8, 10), ("ivf128", 64, 10), ("ivf960", 6, 10),
+                                              ("ivf128", 5, 100)])
+def test_search_fdscanning_ids_equal_oracle(ads, request, fixture, nprobe, K):
+    w, ix = request.getfixturevalue(fixture)
+    ids, dist, probes = ads.search(ix, w.q, K, nprobe, eps0=math.inf, want_probes=True)
+    ids, dist, probes = _np(ids), _np(dist), _np(probes)
+    pr, nbad = _check_probes(w, probes, nprobe)
+    o_ids, o_d, _ = w.oracle_search(pr, K, math.inf, 32, method=oracle.METHOD_FDS)
+    for i in range(w.nq):
+        if list(probes[i]) != list(pr[i]):
+            continue
+        assert tie_band_equal(ids[i], dist[i], o_ids[i], o_d[i]), i
+    assert nbad <= max(1, w.nq // 20)
+
+
+@pytest.mark.parametrize("fixture,nprobe,dd", [("ivf128", 16, 32), ("ivf960", 8, 32), ("ivf960", 8, 16),
+                                               ("ivf960", 8, 64)])
+def test_search_adsampling_recall_matches_oracle(ads, request, fixture, nprobe, dd):
+    w, ix = request.getfixturevalue(fixture)
+    if dd != 32:
+        ix = _build(ads, w, dd=dd)
+    K = 10
+    stats = torch.zeros(ads.NSTATS, dtype=torch.int64, device="cuda")
+    ids, dist, probes = ads.search(ix, w.q, K, nprobe, eps0=2.1, want_probes=True, stats=stats)
+    ids, dist, probes, st = _np(ids), _np(dist), _np(probes), _np(stats)
+    pr, _ = _check_probes(w, probes, nprobe)
+    _, gt = w.gt(K)
+    o_ids, o_d, o_st = w.oracle_search(pr, K, 2.1, dd)
+    # returned distances are the exact distances of the returned ids
+    for i in range(w.nq):
+        v = ids[i] >= 0
+        ex = oracle.exact_dist(w.x[ids[i][v]], w.q[i])
+        assert np.all(np.abs(dist[i][v] - ex) <= 1e-5 * ex)
+    # recall on exact raw-space distances for both sides (ties at the K-th
+    # distance are exact in the integer data and must count as hits)
+    r_gpu = oracle.recall(ids, w.exact(ids), gt, K)
+    r_orc = oracle.recall(o_ids, w.exact(o_ids), gt, K)
+    assert abs(r_gpu - r_orc) <= 0.002 + 1.0 / (w.nq * K)
+    # the same candidates were examined
+    assert st[0] == o_st[:, 0].sum()
+    # ADSampling samples far fewer coordinates than the full scan
+    assert st[1] < 0.6 * st[0] * w.D
+
+
+def test_search_is_batch_independent_with_uneven_k_and_nprobe(ads, ivf128):
+    """A query's result depends only on itself: run alone or in an uneven
+    batch (per-query K and nprobe), the outputs are bit-identical."""
+    w, ix = ivf128
+    rng = np.random.default_rng(5)
+    K = rng.choice([1, 10, 50], size=w.nq).astype(np.int32)
+    npb = rng.integers(1, 40, size=w.nq).astype(np.int32)
+    ids, dist = ads.search(ix, w.q, 50, 40, eps0=2.1, K=K, nprobe=npb)
+    ids, dist = _np(ids), _np(dist)
+    for i in (0, 7, 33):
+        a_ids, a_d = ads.search(ix, w.q[i:i + 1], int(K[i]), int(npb[i]), eps0=2.1)
+        a_ids, a_d = _np(a_ids), _np(a_d)
+        assert np.array_equal(a_ids[0], ids[i, :K[i]])
+        assert np.array_equal(a_d[0], dist[i, :K[i]])
+        assert np.all(ids[i, K[i]:] == -1)
+
+
+def test_search_edge_cases(ads, ivf128):
+    w, ix = ivf128
+    # nq = 0 is a no-op
+    ids, dist = ads.search(ix, w.q[:0], 10, 4)
+    assert ids.shape == (0, 10)
+    # every list probed, K = 1
+    ids, dist = ads.search(ix, w.q[:5], 1, w.nlist, eps0=math.inf)
+    _, gt = w.gt(1)
+    assert np.allclose(_np(dist)[:, 0], gt[:5, 0], rtol=1e-5)
+    # K larger than the candidates available: padding with -1 / inf
+    small = Workload("mix", 300, 3, 128, 32, 77)
+    ix2 = _build(ads, small)
+    ids, dist = ads.search(ix2, small.q, 100, 1, eps0=2.1)
+    ids, dist = _np(ids), _np(dist)
+    for i in range(3):
+        n_avail = np.count_nonzero(ids[i] >= 0)
+        assert n_avail <= 100
+        assert np.all(ids[i, n_avail:] == -1) and np.all(np.isinf(dist[i, n_avail:]))
+        assert np.all(np.diff(dist[i, :n_avail]) >= 0)
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+def test_low_precision_storage_with_rerank(ads, ivf960, storage):
+    """BF16 / FP16 storage, KNN set of 4K on low-precision distances, float32
+    rerank: returned distances are float32-exact, recall stays at the oracle's."""
+    w, _ = ivf960
+    ix = _build(ads, w, storage=storage)
+    K, nprobe = 10, 8
+    ids, dist, probes = ads.search(ix, w.q, K, nprobe, eps0=2.1, rerank=1, want_probes=True)
+    ids, dist, probes = _np(ids), _np(dist), _np(probes)
+    pr, _ = _check_probes(w, probes, nprobe)
+    _, gt = w.gt(K)
+    o_ids, o_d, _ = w.oracle_search(pr, K, 2.1, 32)
+    errs = []
+    ex_all = np.full(ids.shape, np.inf)
+    for i in range(w.nq):
+        v = ids[i] >= 0
+        ex = oracle.exact_dist(w.x[ids[i][v]], w.q[i])
+        ex_all[i][v] = ex
+        errs.extend((np.abs(dist[i][v] - ex) / ex).tolist())
+    assert max(errs) <= 1e-5
+    assert oracle.recall(ids, ex_all, gt, K) >= oracle.recall(o_ids, w.exact(o_ids), gt, K) - 0.01

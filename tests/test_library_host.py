@@ -1,0 +1,74 @@
+"""CPU-side checks of the C ABI library: it loads, exports every entry point
+include/ads.h declares, its host-only QR matches the oracle's, and argument
+validation rejects bad calls before anything touches a GPU."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synthdata as sd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def ads():
+    import paper_2303_09855_amd as m
+    m.load()
+    return m
+
+
+def declared_symbols():
+    with open(os.path.join(ROOT, "include", "ads.h")) as fh:
+        text = fh.read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(ads_[a-z_0-9]+)\(", text, re.M)))
+
+
+def test_header_declares_the_binding_surface(ads):
+    assert declared_symbols() == sorted(ads.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol(ads):
+    lib = ads.load()
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+    assert "gfx950" in ads.version()
+
+
+@pytest.mark.parametrize("D", [8, 128, 960])
+def test_host_rotation_matches_oracle_qr(ads, D):
+    G = sd.gaussian_matrix(D, 1001)
+    P32, P64 = ads.make_rotation(G)
+    ref = oracle.make_rotation(G)
+    assert np.max(np.abs(P64 - ref)) < 1e-12
+    assert np.max(np.abs(P32.astype(np.float64) - ref)) < 1e-7
+    assert np.max(np.abs(P64.T @ P64 - np.eye(D))) < 1e-12
+
+
+def test_rotation_rejects_bad_arguments(ads):
+    lib = ads.load()
+    out = np.zeros(4, dtype=np.float32)
+    assert lib.ads_make_rotation(None, 2, out.ctypes.data_as(ctypes.c_void_p), None) == -1
+    g = np.zeros((2, 2))
+    assert lib.ads_make_rotation(g.ctypes.data_as(ctypes.c_void_p), 0, out.ctypes.data_as(ctypes.c_void_p), None) == -1
+    assert "D must be" in ads.last_error()
+
+
+def test_calls_validate_before_launching(ads):
+    lib = ads.load()
+    # NULL index / pointers are rejected on the host with a message
+    assert lib.ads_search(None, None, 1, None, None, 10, 1, 2.1, 0, 0, None, None, None, None, None, None) == -1
+    assert "index is NULL" in ads.last_error()
+    assert lib.ads_dco_batch(None, None, None, 1, 1.0, 2.1, 32, 0, 0, None, None, None, None, None) == -1
+    out = ctypes.c_void_p()
+    assert lib.ads_ivf_build(None, 10, 128, None, None, 4, None, 32, 0, 1, None, ctypes.byref(out)) == -1
+    assert "must not be NULL" in ads.last_error()
+    assert lib.ads_rotate(None, 128, None, 0, None, None) == 0   # n == 0 is a no-op
+    assert lib.ads_rotate(None, 128, None, 5, None, None) == -1
+    assert lib.ads_index_info(None, None) == -1
+    assert lib.ads_index_free(None) == 0
+    assert lib.ads_search_workspace_size(None, 1, 10, 1, 0) == 0
