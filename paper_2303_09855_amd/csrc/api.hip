@@ -18,9 +18,10 @@ __global__ void probe_select_kernel(const float *qrot, const float *dots, const 
                                     int nlist, int nprobe_max, int32_t *probes);
 __global__ void group_count_kernel(const int32_t *probes, const int32_t *npq, const int32_t *keff,
                                    int nq, int nprobe_max, int nlist, int32_t *cnt);
-__global__ void group_scan_kernel(const int32_t *cnt, int nsweep, int nlist, int32_t *beg,
-                                  int32_t *unit_list, int32_t *unit_beg, int32_t *unit_cnt,
-                                  int32_t *n_units);
+__global__ void group_scan_kernel(const int32_t *cnt, int nsweep, int nlist, int qw, int32_t *beg,
+                                  int32_t *uoff, int32_t *xoff, int32_t *xcnt);
+__global__ void unit_expand_kernel(const int32_t *cnt, const int32_t *beg, const int32_t *uoff, int nsweep,
+                                   int nlist, int qw, int64_t ucap, int4 *units);
 __global__ void group_scatter_kernel(const int32_t *probes, const int32_t *npq, const int32_t *keff,
                                      int nq, int nprobe_max, int nlist, const int32_t *beg,
                                      int32_t *cursor, int2 *qent);
@@ -143,22 +144,23 @@ unsigned grid_for(int64_t n, int64_t cap = 65536) {
     return (unsigned)(g > cap ? cap : g);
 }
 
-// Scan tile: queries per workgroup chunk for a KNN-set capacity.
-int qt_for(int kcap) {
-    if (kcap <= 64) return 32;
-    if (kcap <= 128) return 16;
-    if (kcap <= 256) return 8;
-    if (kcap <= 512) return 4;
-    return 0;
+// Queries per scan unit for a KNN-set capacity (local KNN sets <= 4 KB of LDS).
+int qw_for(int kcap) {
+    for (int qw = 8; qw > 1; qw >>= 1)
+        if (qw * kcap <= 512) return qw;
+    return 1;
 }
+
+constexpr float DENSE_FRAC = 0.5f;
 
 constexpr int KCAP_MAX = 512;
 constexpr int NPROBE_MAX_LIMIT = 8192;
 
 struct SearchLayout {
     size_t off_qrot, off_dots, off_probes, off_kq, off_keff, off_npq, off_r2, off_tk, off_cnt,
-        off_beg, off_cursor, off_ul, off_ub, off_uc, off_nu, off_qent, off_slots, total;
-    int nsweep, kcap;
+        off_beg, off_cursor, off_uoff, off_xoff, off_xcnt, off_units, off_qent, off_slots, total;
+    int nsweep, kcap, qw;
+    int64_t ucap;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -166,6 +168,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 SearchLayout layout_for(const ads_index *ix, int nq, int k_max, int nprobe_max, int rerank) {
     SearchLayout L{};
     L.kcap = k_max * (rerank ? 4 : 1);
+    L.qw = qw_for(L.kcap);
     L.nsweep = num_sweeps(nprobe_max);
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + (bytes ? bytes : 1)); return at; };
@@ -182,10 +185,11 @@ SearchLayout layout_for(const ads_index *ix, int nq, int k_max, int nprobe_max, 
     L.off_cnt = take(sl * sizeof(int32_t));
     L.off_cursor = take(sl * sizeof(int32_t));
     L.off_beg = take(sl * sizeof(int32_t));
-    L.off_ul = take(sl * sizeof(int32_t));
-    L.off_ub = take(sl * sizeof(int32_t));
-    L.off_uc = take(sl * sizeof(int32_t));
-    L.off_nu = take((size_t)L.nsweep * sizeof(int32_t));
+    L.off_uoff = take(sl * sizeof(int32_t));
+    L.off_xoff = take((size_t)L.nsweep * 8 * sizeof(int32_t));
+    L.off_xcnt = take((size_t)L.nsweep * 8 * sizeof(int32_t));
+    L.ucap = ((int64_t)nqs * nprobe_max + L.qw - 1) / L.qw + ix->nlist;
+    L.off_units = take((size_t)L.nsweep * L.ucap * sizeof(int4));
     L.off_qent = take(nqs * nprobe_max * sizeof(int2));
     L.off_slots = take(nqs * nprobe_max * (size_t)L.kcap * sizeof(uint64_t));
     L.total = o;
@@ -512,7 +516,7 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
     HIP_TRY(hipGetLastError(), "pending HIP error");
 
     const SearchLayout L = layout_for(ix, nq, k_max, nprobe_max, rerank);
-    const int qt = qt_for(L.kcap);
+    const int qw = L.qw;
     const int D = ix->D, nlist = ix->nlist;
     const int eff_method = std::isinf(eps0) && method == ADS_METHOD_ADSAMPLING ? ADS_METHOD_FDSCANNING : method;
     unsigned char *ws = reinterpret_cast<unsigned char *>(workspace);
@@ -534,10 +538,10 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
     int32_t *cnt = reinterpret_cast<int32_t *>(ws + L.off_cnt);
     int32_t *cursor = reinterpret_cast<int32_t *>(ws + L.off_cursor);
     int32_t *beg = reinterpret_cast<int32_t *>(ws + L.off_beg);
-    int32_t *ul = reinterpret_cast<int32_t *>(ws + L.off_ul);
-    int32_t *ub = reinterpret_cast<int32_t *>(ws + L.off_ub);
-    int32_t *uc = reinterpret_cast<int32_t *>(ws + L.off_uc);
-    int32_t *nu = reinterpret_cast<int32_t *>(ws + L.off_nu);
+    int32_t *uoff = reinterpret_cast<int32_t *>(ws + L.off_uoff);
+    int32_t *xoff = reinterpret_cast<int32_t *>(ws + L.off_xoff);
+    int32_t *xcnt = reinterpret_cast<int32_t *>(ws + L.off_xcnt);
+    int4 *units = reinterpret_cast<int4 *>(ws + L.off_units);
     int2 *qent = reinterpret_cast<int2 *>(ws + L.off_qent);
     uint64_t *slots = reinterpret_cast<uint64_t *>(ws + L.off_slots);
 
@@ -581,10 +585,12 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
         PhaseTimer t(ADS_PHASE_GROUP, stream);
         hipLaunchKernelGGL(group_count_kernel, dim3(grid_for((int64_t)nq * nprobe_max)), dim3(ADS_WG), 0, stream,
                            probes, npq, keff, nq, nprobe_max, nlist, cnt);
-        hipLaunchKernelGGL(group_scan_kernel, dim3(1), dim3(1024), 0, stream, cnt, L.nsweep, nlist, beg, ul, ub, uc,
-                           nu);
+        hipLaunchKernelGGL(group_scan_kernel, dim3(1), dim3(1024), 0, stream, cnt, L.nsweep, nlist, qw, beg, uoff,
+                           xoff, xcnt);
         hipLaunchKernelGGL(group_scatter_kernel, dim3(grid_for((int64_t)nq * nprobe_max)), dim3(ADS_WG), 0, stream,
                            probes, npq, keff, nq, nprobe_max, nlist, beg, cursor, qent);
+        hipLaunchKernelGGL(unit_expand_kernel, dim3(grid_for(sl)), dim3(ADS_WG), 0, stream, cnt, beg, uoff,
+                           L.nsweep, nlist, qw, L.ucap, units);
         SEARCH_TRY(hipGetLastError(), "grouping");
     }
     // 4. sweeps: list-major scan, then per-query merge
@@ -599,10 +605,9 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
         a.qrot = qrot;
         a.keff = keff;
         a.r2_in = r2;
-        a.unit_list = ul + (size_t)s * nlist;
-        a.unit_beg = ub + (size_t)s * nlist;
-        a.unit_cnt = uc + (size_t)s * nlist;
-        a.n_units = nu + s;
+        a.units = units + (size_t)s * L.ucap;
+        a.xoff = xoff + s * 8;
+        a.xcnt = xcnt + s * 8;
         a.qent = qent;
         a.slots = slots;
         a.stats = reinterpret_cast<unsigned long long *>(stats);
@@ -612,11 +617,16 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
         a.kcap = L.kcap;
         a.D = D;
         a.nb = ix->nb;
-        int64_t units_bound = (int64_t)nq * (rb - ra);
-        const int grid = (int)(units_bound < nlist ? units_bound : nlist);
+        a.dense_frac = DENSE_FRAC;
+        // persistent grid: 8 XCD lanes x P workgroups, P bounded by the units of the sweep
+        const int64_t pairs = (int64_t)nq * (rb - ra);
+        const int64_t units_bound = (pairs + qw - 1) / qw + (pairs < nlist ? pairs : nlist);
+        int64_t P = (units_bound + 7) / 8;
+        if (P > 2048) P = 2048;
+        if (P < 1) P = 1;
         {
             PhaseTimer t(ADS_PHASE_SCAN, stream);
-            SEARCH_TRY(launch_scan(a, ix->storage, ix->dd, qt, grid, stream), "scan");
+            SEARCH_TRY(launch_scan(a, ix->storage, ix->dd, qw, (int)(8 * P), stream), "scan");
         }
         const size_t sh = sizeof(uint64_t) * (size_t)next_pow2(L.kcap);
         PhaseTimer tm(ADS_PHASE_MERGE, stream);

@@ -14,19 +14,19 @@ struct ScanArgs {
     const float *qrot;
     const int32_t *keff;
     const float *r2_in;
-    const int32_t *unit_list;
-    const int32_t *unit_beg;
-    const int32_t *unit_cnt;
-    const int32_t *n_units;
+    const int4 *units;      // this sweep's units, XCD-major: (list, first qent entry, queries, 0)
+    const int32_t *xoff;    // [8] first unit of each XCD's range
+    const int32_t *xcnt;    // [8] number of units of each XCD
     const int2 *qent;
     uint64_t *slots;
     unsigned long long *stats;
     double eps0;
     int method;
     int nprobe_max, kcap, D, nb;
+    float dense_frac;       // pairs alive at or below this fraction switch to the pair list
 };
 
-hipError_t launch_scan(const ScanArgs &a, int dtype, int dd, int qt, int grid, hipStream_t s);
+hipError_t launch_scan(const ScanArgs &a, int dtype, int dd, int qw, int grid, hipStream_t s);
 
 int num_sweeps(int nprobe_max);
 int sweep_begin(int s);

@@ -3,83 +3,117 @@
 // (query, list) pairs by list, per-query merges and the final output.
 //
 // Schedule.  The probe ranks of every query are cut into sweeps
-// [0,1), [1,4), [4,16), [16,64), ...  Each sweep is one list-major launch: a
-// workgroup takes one list and every (query, rank) pair of the sweep that
-// probes it, so the list's vectors are read from HBM once per sweep and
-// reused for all those queries.  Inside a sweep a query's threshold r is the
-// K-th distance of its KNN set after the previous sweeps (+inf before the
-// first merge), lowered further by the K-th distance of the positives the
-// workgroup has found for that query in the current list.  Every threshold
-// used is therefore the exact K-th distance of a set of evaluated candidates
-// (or +inf), which is what the failure analysis of Lemma 3.2 and Corollary 4.2
-// needs.  A per-query merge after each sweep rebuilds the KNN set.  A query's
-// result depends only on that query, never on the rest of the batch.
+// [0,1), [1,4), [4,16), [16,64), ...  Each sweep is one list-major launch:
+// the (query, rank) pairs of the sweep are grouped by list, and a unit of work
+// is one list with up to QW of the queries that probe it, so a list's vectors
+// are fetched from HBM about once per sweep and reused by all its queries.
+// Inside a sweep a query's threshold r is the K-th distance of its KNN set
+// after the previous sweeps (+inf before the first merge), lowered further by
+// the K-th distance of the positives the unit has found for that query in the
+// current list.  Every threshold used is therefore the exact K-th distance of
+// a set of evaluated candidates (or +inf), which is what the failure analysis
+// of Lemma 3.2 and Corollary 4.2 needs.  A per-query merge after each sweep
+// rebuilds the KNN set.  A query's result depends only on that query, never
+// on the rest of the batch.
 //
-// Per workgroup: 64 vectors x QT queries form a tile of DCOs.  Coordinates are
-// taken DD at a time from the blocked layout [block][vector][DD] (Section 5.2
-// generalised).  While many pairs of the tile are alive, each lane owns one
-// vector, keeps its DD coordinates in registers and walks the wave's queries
-// (query coordinates broadcast from LDS).  Once at most 512 pairs survive,
-// they are compacted into an LDS list and processed one pair per thread.
+// Execution.  A unit runs on a workgroup of four waves.  Units are laid out
+// XCD-major: workgroup w serves the units of XCD (w mod 8), so every unit of
+// a list lands on the same XCD and shares that XCD's L2.  The list is cut into
+// 64-vector slices, one slice per wave per round; the waves of a round run
+// independently (wave-private LDS, no workgroup barrier) and the round's
+// positives are folded into the unit's local KNN sets afterwards.  In a slice
+// a lane owns one vector: while at least half of the slice's (vector, query)
+// pairs are alive, the lane keeps the vector's DD coordinates of the current
+// block in registers and walks the unit's queries (query coordinates
+// broadcast from LDS).  Then the surviving pairs are compacted into an LDS
+// list and each lane runs its pairs to the end independently (a per-lane state
+// machine over the remaining blocks: no barrier per block, long chains overlap
+// short ones).
 #include "kernels.h"
 
 namespace ads {
 
-constexpr int VT = 64;          // vectors per tile
-constexpr int LIST_CAP = 512;   // compacted pair list capacity (2 per thread)
+constexpr int SCAN_WAVES = 4;    // waves per workgroup; each takes one 64-vector slice per round
 
-
-template <int DD, int QT>
+template <int DD, int QW>
 struct ScanSmem {
-    static constexpr int QPAD = DD + 4;
-    float qs[QT][QPAD];
-    uint64_t list[LIST_CAP];
-    uint64_t pos[QT][VT];
-    float r2s[QT];
-    int qidx[QT], qrank[QT], qk[QT], pcnt[QT], tkcnt[QT], tkmax[QT];
-    int alive_cnt, list_cnt, list_cnt2;
-    // followed by float coef[nb] and uint64 tk[QT][kcap]
+    static constexpr int LCAP = 32 * QW;   // pairs alive when the dense phase hands over
+    // wave-private
+    float qs[SCAN_WAVES][QW][DD + 4];
+    uint64_t list[SCAN_WAVES][2][LCAP];
+    uint64_t pos[SCAN_WAVES][QW][64];
+    int pcnt[SCAN_WAVES][QW];
+    // shared by the unit
+    float r2s[QW];
+    int qidx[QW], qrank[QW], qk[QW], tkcnt[QW], tkmax[QW];
+    // followed by float coef[nb] and uint64 tk[QW][kcap]
 };
 
-template <int DT, int DD, int QT>
-__global__ __launch_bounds__(ADS_WG) void scan_kernel(ScanArgs a) {
-    constexpr int QPW = QT / 4;
+// Orders this wave's LDS accesses (lanes of one wave run in lockstep).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int DT, int DD>
+__device__ __forceinline__ float block_partial(const unsigned char *op, const float *qp, float s) {
+#pragma unroll
+    for (int k0 = 0; k0 < DD; k0 += 8) {
+        float o[8];
+        load_elems<DT, 8>(op + k0 * Elem<DT>::bytes, o);
+        const float4 q0 = *reinterpret_cast<const float4 *>(qp + k0);
+        const float4 q1 = *reinterpret_cast<const float4 *>(qp + k0 + 4);
+        const float qv[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            float df = o[k] - qv[k];
+            s = __fmaf_rn(df, df, s);
+        }
+    }
+    return s;
+}
+
+template <int DT, int DD, int QW>
+__global__ __launch_bounds__(64 * SCAN_WAVES) void scan_kernel(ScanArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    ScanSmem<DD, QT> &sm = *reinterpret_cast<ScanSmem<DD, QT> *>(smem_raw);
-    float *coef = reinterpret_cast<float *>(smem_raw + sizeof(ScanSmem<DD, QT>));
+    ScanSmem<DD, QW> &sm = *reinterpret_cast<ScanSmem<DD, QW> *>(smem_raw);
+    float *coef = reinterpret_cast<float *>(smem_raw + sizeof(ScanSmem<DD, QW>));
     uint64_t *tk = reinterpret_cast<uint64_t *>(
-        smem_raw + ((sizeof(ScanSmem<DD, QT>) + sizeof(float) * a.nb + 15) & ~(size_t)15));
+        smem_raw + ((sizeof(ScanSmem<DD, QW>) + sizeof(float) * a.nb + 15) & ~(size_t)15));
 
-    const int u = blockIdx.x;
-    if (u >= *a.n_units) return;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int x = blockIdx.x & 7;
+    const int P = gridDim.x >> 3;
+    const int cntx = a.xcnt[x], basex = a.xoff[x];
+    if ((int)(blockIdx.x >> 3) >= cntx) return;
     const int D = a.D, nb = a.nb, kcap = a.kcap;
-    const int l = a.unit_list[u];
-    const int beg = a.unit_beg[u], cnt = a.unit_cnt[u];
-    const int64_t off = a.list_off[l];
-    const int nl = (int)(a.list_off[l + 1] - off);
     constexpr int EB = Elem<DT>::bytes;
-    const unsigned char *lbase = reinterpret_cast<const unsigned char *>(a.data) + off * (int64_t)D * EB;
+    const uint64_t lanemask_lt = (1ull << lane) - 1ull;
+    float(*qs)[DD + 4] = sm.qs[w];
+    int *pcnt = sm.pcnt[w];
 
-    for (int b = tid; b < nb; b += ADS_WG) {
+    for (int b = tid; b < nb; b += 64 * SCAN_WAVES) {
         int d = (b + 1) * DD;
         coef[b] = d < D ? test_coef(d, D, a.eps0, a.method) : 0.f;
     }
-
     unsigned long long my_dims = 0, my_pos = 0, my_dcos = 0;
 
-    for (int c0 = 0; c0 < cnt; c0 += QT) {
-        const int qc = min(QT, cnt - c0);
-        if (tid < QT) {
-            int k = 0;
+    for (int k = blockIdx.x >> 3; k < cntx; k += P) {
+        const int4 un = a.units[basex + k];
+        const int l = un.x, qbeg = un.y, qc = un.z;
+        const int64_t off = a.list_off[l];
+        const int nl = (int)(a.list_off[l + 1] - off);
+        const unsigned char *lbase = reinterpret_cast<const unsigned char *>(a.data) + off * (int64_t)D * EB;
+        if (tid < QW) {
+            int kq = 0;
             if (tid < qc) {
-                int2 e = a.qent[beg + c0 + tid];
+                const int2 e = a.qent[qbeg + tid];
                 sm.qidx[tid] = e.x;
                 sm.qrank[tid] = e.y;
-                k = a.keff[e.x];
+                kq = a.keff[e.x];
                 sm.r2s[tid] = a.r2_in[e.x];
             }
-            sm.qk[tid] = k;
+            sm.qk[tid] = kq;
             sm.tkcnt[tid] = 0;
             sm.tkmax[tid] = 0;
         }
@@ -90,140 +124,176 @@ __global__ __launch_bounds__(ADS_WG) void scan_kernel(ScanArgs a) {
             my_dcos += (unsigned long long)act * (unsigned long long)nl;
         }
 
-        for (int vc = 0; vc < nl; vc += VT) {
-            if (tid < QT) sm.pcnt[tid] = 0;
-            if (tid == 0) { sm.alive_cnt = 0; sm.list_cnt = 0; }
+        for (int r0 = 0; r0 < nl; r0 += 64 * SCAN_WAVES) {
+            // ---- this wave's slice: vectors [vc, vc + 64) ----
+            const int vc = r0 + w * 64;
+            if (lane < QW) pcnt[lane] = 0;
             const int v = vc + lane;
             const bool vvalid = v < nl;
-            float S[QPW];
+            float S[QW];
             uint32_t alive = 0;
 #pragma unroll
-            for (int jj = 0; jj < QPW; ++jj) {
+            for (int jj = 0; jj < QW; ++jj) {
                 S[jj] = 0.f;
-                int j = wave * QPW + jj;
-                if (vvalid && j < qc && sm.qk[j] > 0) alive |= 1u << jj;
+                if (vvalid && jj < qc && sm.qk[jj] > 0) alive |= 1u << jj;
             }
-            bool dense = true;
-            __syncthreads();
-            for (int b = 0; b < nb; ++b) {
-                // stage the chunk's query coordinates of block b
-                for (int i = tid; i < QT * (DD / 4); i += ADS_WG) {
-                    int j = i / (DD / 4), k4 = (i % (DD / 4)) * 4;
-                    if (j < qc) {
-                        float4 t = *reinterpret_cast<const float4 *>(a.qrot + (int64_t)sm.qidx[j] * D + b * DD + k4);
-                        sm.qs[j][k4 + 0] = t.x; sm.qs[j][k4 + 1] = t.y;
-                        sm.qs[j][k4 + 2] = t.z; sm.qs[j][k4 + 3] = t.w;
+            int tile_pairs = 0;
+#pragma unroll
+            for (int jj = 0; jj < QW; ++jj) tile_pairs += __popcll(__ballot((alive >> jj) & 1u));
+            int b = 0, m = 0;
+            bool sparse = false;
+            wave_sync();
+            // dense phase: lane = vector, the unit's queries in turn
+            for (; tile_pairs > 0 && b < nb; ++b) {
+                float o[DD];
+                if (alive) load_elems<DT, DD>(lbase + ((int64_t)b * nl * DD + (int64_t)v * DD) * EB, o);
+                for (int i = lane; i < QW * (DD / 4); i += 64) {
+                    const int jj = i / (DD / 4), k4 = (i % (DD / 4)) * 4;
+                    if (jj < qc) {
+                        const float4 t = *reinterpret_cast<const float4 *>(a.qrot + (int64_t)sm.qidx[jj] * D + b * DD + k4);
+                        qs[jj][k4 + 0] = t.x; qs[jj][k4 + 1] = t.y;
+                        qs[jj][k4 + 2] = t.z; qs[jj][k4 + 3] = t.w;
                     }
                 }
-                __syncthreads();
+                wave_sync();
                 const int d = (b + 1) * DD;
                 const float cf = coef[b];
-                if (dense) {
-                    if (alive) {
-                        float o[DD];
-                        load_elems<DT, DD>(lbase + ((int64_t)b * nl * DD + (int64_t)v * DD) * EB, o);
+                if (alive) {
 #pragma unroll
-                        for (int jj = 0; jj < QPW; ++jj) {
-                            if (!((alive >> jj) & 1u)) continue;
-                            const int j = wave * QPW + jj;
-                            float s = S[jj];
+                    for (int jj = 0; jj < QW; ++jj) {
+                        if (!((alive >> jj) & 1u)) continue;
+                        float s = S[jj];
 #pragma unroll
-                            for (int k = 0; k < DD; ++k) {
-                                float df = o[k] - sm.qs[j][k];
-                                s = __fmaf_rn(df, df, s);
-                            }
-                            S[jj] = s;
-                            if (d < D) {
-                                if (test_reject(s, cf, sm.r2s[j])) {
-                                    alive &= ~(1u << jj);
-                                    my_dims += d;
-                                }
-                            } else {
-                                alive &= ~(1u << jj);
-                                my_dims += D;
-                                if (s <= sm.r2s[j]) {
-                                    int p = atomicAdd(&sm.pcnt[j], 1);
-                                    sm.pos[j][p] = make_key(s, (uint32_t)a.ids[off + v]);
-                                    ++my_pos;
-                                }
-                            }
-                        }
-                    }
-                    if (d >= D) break;
-                    int na = __popc(alive);
-                    if (na) atomicAdd(&sm.alive_cnt, na);
-                    __syncthreads();
-                    const int n_alive = sm.alive_cnt;
-                    if (n_alive == 0) break;
-                    if (n_alive <= LIST_CAP) {
-                        // switch to the compacted pair list
-#pragma unroll
-                        for (int jj = 0; jj < QPW; ++jj) {
-                            if ((alive >> jj) & 1u) {
-                                int p = atomicAdd(&sm.list_cnt, 1);
-                                uint32_t tag = (uint32_t)((wave * QPW + jj) << 6 | lane);
-                                sm.list[p] = ((uint64_t)__float_as_uint(S[jj]) << 32) | tag;
-                            }
-                        }
-                        alive = 0;
-                        dense = false;
-                    }
-                    __syncthreads();
-                    if (tid == 0) sm.alive_cnt = 0;
-                } else {
-                    const int m = sm.list_cnt;
-                    uint64_t e0 = KEY_NONE, e1 = KEY_NONE;
-                    if (tid < m) e0 = sm.list[tid];
-                    if (tid + ADS_WG < m) e1 = sm.list[tid + ADS_WG];
-                    __syncthreads();
-                    if (tid == 0) sm.list_cnt = 0;
-                    __syncthreads();
-#pragma unroll
-                    for (int t = 0; t < 2; ++t) {
-                        uint64_t e = t == 0 ? e0 : e1;
-                        if (e == KEY_NONE) continue;
-                        const uint32_t tag = (uint32_t)e;
-                        const int vl = tag & 63, j = (int)(tag >> 6);
-                        const int vv = vc + vl;
-                        float s = __uint_as_float((uint32_t)(e >> 32));
-                        float o[DD];
-                        load_elems<DT, DD>(lbase + ((int64_t)b * nl * DD + (int64_t)vv * DD) * EB, o);
-#pragma unroll
-                        for (int k = 0; k < DD; ++k) {
-                            float df = o[k] - sm.qs[j][k];
+                        for (int kk = 0; kk < DD; ++kk) {
+                            float df = o[kk] - qs[jj][kk];
                             s = __fmaf_rn(df, df, s);
                         }
+                        S[jj] = s;
                         if (d < D) {
-                            if (test_reject(s, cf, sm.r2s[j])) {
+                            if (test_reject(s, cf, sm.r2s[jj])) {
+                                alive &= ~(1u << jj);
                                 my_dims += d;
-                            } else {
-                                int p = atomicAdd(&sm.list_cnt, 1);
-                                sm.list[p] = ((uint64_t)__float_as_uint(s) << 32) | tag;
                             }
                         } else {
+                            alive &= ~(1u << jj);
                             my_dims += D;
-                            if (s <= sm.r2s[j]) {
-                                int p = atomicAdd(&sm.pcnt[j], 1);
-                                sm.pos[j][p] = make_key(s, (uint32_t)a.ids[off + vv]);
+                            if (s <= sm.r2s[jj]) {
+                                const int p = atomicAdd(&pcnt[jj], 1);
+                                sm.pos[w][jj][p] = make_key(s, (uint32_t)a.ids[off + v]);
                                 ++my_pos;
                             }
                         }
                     }
-                    __syncthreads();
-                    if (d >= D || sm.list_cnt == 0) break;
+                }
+                wave_sync();
+                if (d >= D) break;
+                int na = 0;
+#pragma unroll
+                for (int jj = 0; jj < QW; ++jj) na += __popcll(__ballot((alive >> jj) & 1u));
+                if (na == 0) break;
+                if (2 * na <= tile_pairs) {
+                    uint64_t *list = sm.list[w][0];
+                    int base = 0;
+#pragma unroll
+                    for (int jj = 0; jj < QW; ++jj) {
+                        const bool bit = (alive >> jj) & 1u;
+                        const uint64_t msk = __ballot(bit);
+                        if (bit) {
+                            const int p = base + __popcll(msk & lanemask_lt);
+                            list[p] = ((uint64_t)__float_as_uint(S[jj]) << 32) | (uint32_t)(jj << 6 | lane);
+                        }
+                        base += __popcll(msk);
+                    }
+                    m = base;
+                    sparse = true;
+                    ++b;
+                    break;
+                }
+            }
+            // sparse phase: all surviving pairs sit at the same next block
+            // bcur.  With n pairs left, each pair takes G = 64 / n lanes (a
+            // power of two) that evaluate blocks bcur .. bcur+G-1 at once; a
+            // segmented prefix scan gives S at every block boundary and the
+            // first rejecting block is found with a ballot, so the decisions
+            // are those of testing block by block.  Survivors advance by G
+            // blocks together and are compacted into the other list.
+            if (sparse) {
+                int bcur = b, cur = 0, n = m;
+                while (n > 0 && bcur < nb) {
+                    wave_sync();
+                    int G = 1;
+                    while (G * 2 * n <= 64 && G * 2 <= nb - bcur) G *= 2;
+                    const int ppr = 64 / G;                 // pairs per round
+                    const int gi = lane & (G - 1);
+                    const uint64_t *src = sm.list[w][cur];
+                    uint64_t *dst = sm.list[w][cur ^ 1];
+                    int nout = 0;
+                    for (int r0p = 0; r0p < n; r0p += ppr) {
+                        const int pi = r0p + lane / G;
+                        const bool pv = pi < n;
+                        const uint64_t en = pv ? src[pi] : 0ull;
+                        const float s0 = __uint_as_float((uint32_t)(en >> 32));
+                        const int jj = (int)(((uint32_t)en >> 6) & 7u), vv = (int)(en & 63u);
+                        const int blk = bcur + gi;
+                        const bool bv = pv && blk < nb;
+                        float part = 0.f;
+                        if (bv) {
+                            const unsigned char *op = lbase + ((int64_t)blk * nl * DD + (int64_t)(vc + vv) * DD) * EB;
+                            part = block_partial<DT, DD>(op, a.qrot + (int64_t)sm.qidx[jj] * D + blk * DD, 0.f);
+                        }
+                        float sc = part;
+                        for (int o = 1; o < G; o <<= 1) {
+                            const float tv = __shfl_up(sc, o, G);
+                            if (gi >= o) sc += tv;
+                        }
+                        const float sb = s0 + sc;
+                        const int d = (blk + 1) * DD;
+                        const float r2 = pv ? sm.r2s[jj] : 0.f;
+                        const bool rej = bv && d < D && test_reject(sb, coef[bv ? blk : 0], r2);
+                        const uint64_t rm = __ballot(rej);
+                        const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (lane & ~(G - 1)));
+                        const uint64_t grm = rm & gmask;
+                        // the group's last block and the value of S there
+                        const int glast = min(G, nb - bcur) - 1;
+                        const float slast = __shfl(sb, (lane & ~(G - 1)) + glast, 64);
+                        bool keep = false;
+                        if (pv && gi == 0) {
+                            if (grm) {
+                                const int first = __ffsll((long long)grm) - 1 - (lane & ~(G - 1));
+                                my_dims += (unsigned long long)(bcur + first + 1) * DD;
+                            } else if (bcur + glast + 1 >= nb) {
+                                my_dims += D;
+                                if (slast <= r2) {
+                                    const int p = atomicAdd(&pcnt[jj], 1);
+                                    sm.pos[w][jj][p] = make_key(slast, (uint32_t)a.ids[off + vc + vv]);
+                                    ++my_pos;
+                                }
+                            } else {
+                                keep = true;
+                            }
+                        }
+                        const uint64_t km = __ballot(keep);
+                        if (keep) {
+                            const int p = nout + __popcll(km & lanemask_lt);
+                            dst[p] = ((uint64_t)__float_as_uint(slast) << 32) | (uint32_t)(en & 0xffffffffu);
+                        }
+                        nout += __popcll(km);
+                    }
+                    n = nout;
+                    cur ^= 1;
+                    bcur += G;
                 }
             }
             __syncthreads();
-            // fold this tile's positives into each query's local KNN set
-            if (tid < qc) {
-                const int j = tid;
-                const int K = sm.qk[j];
-                if (K > 0) {
-                    uint64_t *mytk = tk + (int64_t)j * kcap;
-                    int c = sm.tkcnt[j], mx = sm.tkmax[j];
-                    const int np = sm.pcnt[j];
+            // fold the round's positives into each query's local KNN set
+            if (tid < qc && sm.qk[tid] > 0) {
+                const int j = tid, K = sm.qk[j];
+                uint64_t *mytk = tk + (int64_t)j * kcap;
+                int c = sm.tkcnt[j], mx = sm.tkmax[j];
+                for (int ww = 0; ww < SCAN_WAVES; ++ww) {
+                    const int np = sm.pcnt[ww][j];
                     for (int p = 0; p < np; ++p) {
-                        uint64_t key = sm.pos[j][p];
+                        const uint64_t key = sm.pos[ww][j][p];
                         if (c < K) {
                             mytk[c++] = key;
                             if (c == K) {
@@ -236,82 +306,82 @@ __global__ __launch_bounds__(ADS_WG) void scan_kernel(ScanArgs a) {
                             for (int t = 1; t < K; ++t) if (mytk[t] > mytk[mx]) mx = t;
                         }
                     }
-                    sm.tkcnt[j] = c;
-                    sm.tkmax[j] = mx;
-                    if (c == K) {
-                        float kth = key_dist2(mytk[mx]);
-                        if (kth < sm.r2s[j]) sm.r2s[j] = kth;
-                    }
+                }
+                sm.tkcnt[j] = c;
+                sm.tkmax[j] = mx;
+                if (c == K) {
+                    const float kth = key_dist2(mytk[mx]);
+                    if (kth < sm.r2s[j]) sm.r2s[j] = kth;
                 }
             }
             __syncthreads();
         }
-        // publish the local KNN sets of this chunk
-        for (int i = tid; i < qc * kcap; i += ADS_WG) {
+        // publish the unit's per-query KNN sets for the merge
+        for (int i = tid; i < qc * kcap; i += 64 * SCAN_WAVES) {
             const int j = i / kcap, t = i % kcap;
-            uint64_t key = (sm.qk[j] > 0 && t < sm.tkcnt[j]) ? tk[(int64_t)j * kcap + t] : KEY_NONE;
+            const uint64_t key = (sm.qk[j] > 0 && t < sm.tkcnt[j]) ? tk[(int64_t)j * kcap + t] : KEY_NONE;
             a.slots[((int64_t)sm.qidx[j] * a.nprobe_max + sm.qrank[j]) * kcap + t] = key;
         }
         __syncthreads();
     }
 
     if (a.stats) {
-        // wave reductions, then one atomic per wave
         for (int o = 32; o > 0; o >>= 1) {
             my_dims += __shfl_down(my_dims, o);
             my_pos += __shfl_down(my_pos, o);
+            my_dcos += __shfl_down(my_dcos, o);
         }
         if (lane == 0) {
             atomicAdd(a.stats + ADS_STAT_DIMS, my_dims);
             atomicAdd(a.stats + ADS_STAT_BYTES, my_dims * (unsigned long long)EB);
             atomicAdd(a.stats + ADS_STAT_POSITIVES, my_pos);
-            if (tid == 0) atomicAdd(a.stats + ADS_STAT_DCOS, my_dcos);
+            atomicAdd(a.stats + ADS_STAT_DCOS, my_dcos);
         }
     }
 }
 
-template <int DD, int QT>
+template <int DD, int QW>
 size_t scan_smem_bytes(int nb, int kcap) {
-    size_t s = sizeof(ScanSmem<DD, QT>) + sizeof(float) * nb;
+    size_t s = sizeof(ScanSmem<DD, QW>) + sizeof(float) * nb;
     s = (s + 15) & ~(size_t)15;
-    return s + sizeof(uint64_t) * (size_t)QT * kcap;
+    return s + sizeof(uint64_t) * (size_t)QW * kcap;
 }
 
-template <int DT, int DD, int QT>
+template <int DT, int DD, int QW>
 hipError_t launch_scan_t(const ScanArgs &a, int grid, hipStream_t s) {
-    size_t sh = scan_smem_bytes<DD, QT>(a.nb, a.kcap);
-    if (sh > 160 * 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((scan_kernel<DT, DD, QT>), dim3(grid), dim3(ADS_WG), sh, s, a);
+    size_t sh = scan_smem_bytes<DD, QW>(a.nb, a.kcap);
+    if (sh > 64 * 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((scan_kernel<DT, DD, QW>), dim3(grid), dim3(64 * SCAN_WAVES), sh, s, a);
     return hipGetLastError();
 }
 
 template <int DT, int DD>
-hipError_t launch_scan_q(const ScanArgs &a, int qt, int grid, hipStream_t s) {
-    switch (qt) {
-        case 32: return launch_scan_t<DT, DD, 32>(a, grid, s);
-        case 16: return launch_scan_t<DT, DD, 16>(a, grid, s);
+hipError_t launch_scan_q(const ScanArgs &a, int qw, int grid, hipStream_t s) {
+    switch (qw) {
         case 8: return launch_scan_t<DT, DD, 8>(a, grid, s);
         case 4: return launch_scan_t<DT, DD, 4>(a, grid, s);
+        case 2: return launch_scan_t<DT, DD, 2>(a, grid, s);
+        case 1: return launch_scan_t<DT, DD, 1>(a, grid, s);
     }
     return hipErrorInvalidValue;
 }
 
 template <int DT>
-hipError_t launch_scan_d(const ScanArgs &a, int dd, int qt, int grid, hipStream_t s) {
+hipError_t launch_scan_d(const ScanArgs &a, int dd, int qw, int grid, hipStream_t s) {
     switch (dd) {
-        case 8: return launch_scan_q<DT, 8>(a, qt, grid, s);
-        case 16: return launch_scan_q<DT, 16>(a, qt, grid, s);
-        case 32: return launch_scan_q<DT, 32>(a, qt, grid, s);
-        case 64: return launch_scan_q<DT, 64>(a, qt, grid, s);
+        case 8: return launch_scan_q<DT, 8>(a, qw, grid, s);
+        case 16: return launch_scan_q<DT, 16>(a, qw, grid, s);
+        case 32: return launch_scan_q<DT, 32>(a, qw, grid, s);
+        case 64: return launch_scan_q<DT, 64>(a, qw, grid, s);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_scan(const ScanArgs &a, int dtype, int dd, int qt, int grid, hipStream_t s) {
+hipError_t launch_scan(const ScanArgs &a, int dtype, int dd, int qw, int grid, hipStream_t s) {
     switch (dtype) {
-        case ADS_F32: return launch_scan_d<ADS_F32>(a, dd, qt, grid, s);
-        case ADS_BF16: return launch_scan_d<ADS_BF16>(a, dd, qt, grid, s);
-        case ADS_F16: return launch_scan_d<ADS_F16>(a, dd, qt, grid, s);
+        case ADS_F32: return launch_scan_d<ADS_F32>(a, dd, qw, grid, s);
+        case ADS_BF16: return launch_scan_d<ADS_BF16>(a, dd, qw, grid, s);
+        case ADS_F16: return launch_scan_d<ADS_F16>(a, dd, qw, grid, s);
     }
     return hipErrorInvalidValue;
 }
@@ -420,52 +490,101 @@ __global__ void group_count_kernel(const int32_t *probes, const int32_t *npq, co
     }
 }
 
-// One workgroup of 1024 threads: exclusive prefix of cnt over (sweep, list)
-// (entry offsets) and, per sweep, the compacted list of non-empty lists.
-__global__ __launch_bounds__(1024) void group_scan_kernel(const int32_t *cnt, int nsweep, int nlist,
-                                                          int32_t *beg, int32_t *unit_list,
-                                                          int32_t *unit_beg, int32_t *unit_cnt,
-                                                          int32_t *n_units) {
-    __shared__ int32_t sa[1024], sb[1024];
-    __shared__ int32_t carry_a, carry_b;
-    if (threadIdx.x == 0) carry_a = 0;
+// Position i of the XCD-major order -> list id: lists x, x+8, x+16, ... form
+// block x of the order.
+__device__ inline int xcd_major_list(int i, int nlist) {
+    int start = 0;
+    for (int x = 0; x < 8; ++x) {
+        const int nx = x < nlist ? (nlist - x + 7) / 8 : 0;
+        if (i < start + nx) return x + 8 * (i - start);
+        start += nx;
+    }
+    return -1;
+}
+
+// One workgroup of 1024 threads.  Per sweep: exclusive prefix of cnt over
+// lists (entry offsets into qent, continuing across sweeps) and the unit
+// offsets of every list in XCD-major order (ceil(cnt / qw) units per list),
+// with the first unit and the unit count of every XCD.
+__global__ __launch_bounds__(1024) void group_scan_kernel(const int32_t *cnt, int nsweep, int nlist, int qw,
+                                                          int32_t *beg, int32_t *uoff, int32_t *xoff,
+                                                          int32_t *xcnt) {
+    __shared__ int32_t sa[1024];
+    __shared__ int32_t carry;
+    __shared__ int32_t xfirst[9];
+    if (threadIdx.x == 0) carry = 0;
     __syncthreads();
     for (int s = 0; s < nsweep; ++s) {
-        if (threadIdx.x == 0) carry_b = 0;
-        __syncthreads();
+        // entry offsets in natural list order
         for (int l0 = 0; l0 < nlist; l0 += 1024) {
-            int l = l0 + threadIdx.x;
-            int c = l < nlist ? cnt[(int64_t)s * nlist + l] : 0;
+            const int l = l0 + threadIdx.x;
+            const int c = l < nlist ? cnt[(int64_t)s * nlist + l] : 0;
             sa[threadIdx.x] = c;
-            sb[threadIdx.x] = c > 0;
             __syncthreads();
             for (int o = 1; o < 1024; o <<= 1) {
-                int xa = threadIdx.x >= o ? sa[threadIdx.x - o] : 0;
-                int xb = threadIdx.x >= o ? sb[threadIdx.x - o] : 0;
+                const int xa = threadIdx.x >= o ? sa[threadIdx.x - o] : 0;
                 __syncthreads();
                 sa[threadIdx.x] += xa;
-                sb[threadIdx.x] += xb;
                 __syncthreads();
             }
-            int ea = carry_a + sa[threadIdx.x] - c;       // exclusive
-            int eb = carry_b + sb[threadIdx.x] - (c > 0);
-            if (l < nlist) {
-                beg[(int64_t)s * nlist + l] = ea;
-                if (c > 0) {
-                    unit_list[(int64_t)s * nlist + eb] = l;
-                    unit_beg[(int64_t)s * nlist + eb] = ea;
-                    unit_cnt[(int64_t)s * nlist + eb] = c;
-                }
-            }
+            if (l < nlist) beg[(int64_t)s * nlist + l] = carry + sa[threadIdx.x] - c;
             __syncthreads();
-            if (threadIdx.x == 1023) {
-                carry_a += sa[1023];
-                carry_b += sb[1023];
-            }
+            if (threadIdx.x == 1023) carry += sa[1023];
             __syncthreads();
         }
-        if (threadIdx.x == 0) n_units[s] = carry_b;
+        // unit offsets in XCD-major list order
+        __shared__ int32_t ucarry;
+        if (threadIdx.x == 0) ucarry = 0;
+        if (threadIdx.x < 9) xfirst[threadIdx.x] = -1;
         __syncthreads();
+        for (int i0 = 0; i0 < nlist; i0 += 1024) {
+            const int i = i0 + threadIdx.x;
+            const int l = i < nlist ? xcd_major_list(i, nlist) : -1;
+            const int c = l >= 0 ? cnt[(int64_t)s * nlist + l] : 0;
+            const int ng = (c + qw - 1) / qw;
+            sa[threadIdx.x] = ng;
+            __syncthreads();
+            for (int o = 1; o < 1024; o <<= 1) {
+                const int xa = threadIdx.x >= o ? sa[threadIdx.x - o] : 0;
+                __syncthreads();
+                sa[threadIdx.x] += xa;
+                __syncthreads();
+            }
+            const int ex = ucarry + sa[threadIdx.x] - ng;
+            if (l >= 0) {
+                uoff[(int64_t)s * nlist + l] = ex;
+                const int xl = l & 7;
+                if (l == xl) xfirst[xl] = ex;   // the first list of block xl
+            }
+            __syncthreads();
+            if (threadIdx.x == 1023) ucarry += sa[1023];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            int prev_end = ucarry;
+            for (int x = 7; x >= 0; --x) {
+                const int f = xfirst[x] >= 0 ? xfirst[x] : prev_end;
+                xoff[s * 8 + x] = f;
+                xcnt[s * 8 + x] = prev_end - f;
+                prev_end = f;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Writes the units of every (sweep, list): (list, first entry, query count).
+__global__ void unit_expand_kernel(const int32_t *cnt, const int32_t *beg, const int32_t *uoff, int nsweep,
+                                   int nlist, int qw, int64_t ucap, int4 *units) {
+    const int64_t tot = (int64_t)nsweep * nlist;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = cnt[i];
+        if (c <= 0) continue;
+        const int s = (int)(i / nlist), l = (int)(i % nlist);
+        const int b0 = beg[i];
+        int4 *u = units + (int64_t)s * ucap + uoff[i];
+        for (int g = 0; g * qw < c; ++g) u[g] = make_int4(l, b0 + g * qw, min(qw, c - g * qw), 0);
     }
 }
 
