@@ -27,7 +27,10 @@ if ROOT not in sys.path:
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-FP32_VECTOR_PEAK_TFLOPS = 157.3
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz: the FP32 vector rate
+# without packed FP32 instructions (which this library does not emit); the
+# published 157.3 TFLOP/s counts packed FP32.
+FP32_VALU_PEAK_TFLOPS = 78.6
 
 NPROBE_GRID = [8, 16, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096,
                6144, 8192]
@@ -54,6 +57,12 @@ def parse():
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fds", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 1 GiB device-to-device copy first (reference kernel "
+                         "of known size for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
+    ap.add_argument("--nprobe", type=int, default=None,
+                    help="use this nprobe for both methods instead of searching for the "
+                         "smallest one that reaches the target recall")
     return ap.parse_args()
 
 
@@ -111,6 +120,14 @@ def main() -> int:
     log(f"index built in {time.time() - t0:.1f}s ({info['device_bytes'] / 1e9:.2f} GB, "
         f"max list {info['max_list']})")
     qd = torch.as_tensor(q).cuda()
+    if args.calibrate_copy:
+        src = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("calibration copy: 1 GiB read + 1 GiB written")
 
     def run(nprobe, eps0, stats=None):
         ids, dist = ads.search(ix, qd, K, nprobe, eps0=eps0, rerank=rerank, stats=stats)
@@ -123,6 +140,10 @@ def main() -> int:
         return oracle.recall(ids, exact_for(x, q, ids), gt, K)
 
     def operating_point(eps0, label):
+        if args.nprobe:
+            r = recall_at(args.nprobe, eps0)
+            log(f"{label}: nprobe {args.nprobe:5d} recall@{K} {r:.4f} (fixed)")
+            return args.nprobe, r
         grid = [p for p in NPROBE_GRID if p < w.nlist] + [w.nlist]
         best = None
         for p in grid:
@@ -178,6 +199,7 @@ def main() -> int:
     achieved_gbs = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
     flops = 3.0 * dims  # one subtract and one fused multiply-add per sampled coordinate
     achieved_tflops = flops / (scan_ms_step * 1e-3) / 1e12
+    traffic = scan_traffic_from_profile()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -206,19 +228,45 @@ def main() -> int:
         "speedup_vs_fdscanning": round(fds["ms_per_step"] / ms_ads, 3) if fds else None,
         "fdscanning": fds,
         "phase_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in ph_ads.items()},
-        "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "scan_kernel", "avg_launch_ms": round(avg_launch_ms, 4),
+        "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3),
+                     "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved_tflops / FP32_VALU_PEAK_TFLOPS, 4),
+                     "traffic": traffic, "kernel": "scan_kernel",
+                     "avg_launch_ms": round(avg_launch_ms, 4),
                      "launches_per_step": launches_per_step,
-                     "alg_bytes_per_launch": round(bytes_per_launch, 1)},
-        "roofline_alu": {"bound": "alu", "achieved": round(achieved_tflops, 3),
-                         "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                         "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 4)},
+                     "alg_flops_per_launch": round(flops / max(1.0, launches_per_step), 1)},
+        "roofline_hbm_algorithmic": {"bound": "hbm", "achieved": round(achieved_gbs, 1),
+                                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                     "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+                                     "alg_bytes_per_launch": round(bytes_per_launch, 1),
+                                     "note": "bytes the DCOs need (sampled dims x 4 B); a list "
+                                             "tile is fetched once and reused by its queries, so "
+                                             "this exceeds the HBM traffic"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     ix.free()
     return 0
+
+
+def scan_traffic_from_profile():
+    """HBM bytes per scan launch from the committed counter summary, or None
+    when the scan kernel source changed since the counters were taken."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "scan_kernel_ivf_d960_counters.txt")
+    src = os.path.join(ROOT, "paper_2303_09855_amd", "csrc", "scan.hip")
+    try:
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        fields = {}
+        for line in open(prof):
+            if ":" in line:
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+        if fields.get("scan_source_sha256") != sha:
+            return None
+        return float(fields["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(w, x, q, G, cent, assign, nprobe, K, args):

@@ -225,6 +225,25 @@ uint64_t ads_search_workspace_size(const ads_index *ix, int32_t nq, int32_t k_ma
                                    int32_t nprobe_max, int32_t rerank);
 
 /* --------------------------------------------------------------------------
+ * Scheduling knobs of the scan (no effect on what a DCO decides).
+ * -------------------------------------------------------------------------- */
+
+typedef struct {
+    float dense_frac;         /* (0, 0.25]: a 64-vector slice leaves the register-dense
+                                 phase once at most this fraction of its (vector, query)
+                                 pairs is alive.  Default 0.125. */
+    int32_t queries_per_unit; /* 1, 2, 4, 8 or 16 queries per work unit; 0 = the largest of
+                                 1..8 whose KNN sets fit in 4 KB of LDS.  Default 0. */
+    int32_t sweep_log2;       /* probe ranks are scanned in sweeps [0,1), [1,g), [g,g^2), ...
+                                 with g = 2^sweep_log2, sweep_log2 in [1, 6].  Default 3. */
+} ads_tuning;
+
+/* ads_set_tuning / ads_get_tuning -- HOST, per thread: knobs for later
+ * ads_search calls issued by this thread.  ADS_EINVAL on values out of range. */
+ads_status ads_set_tuning(const ads_tuning *t);
+ads_status ads_get_tuning(ads_tuning *t);
+
+/* --------------------------------------------------------------------------
  * Optional per-phase timing with HIP events (off by default).
  * -------------------------------------------------------------------------- */
 

@@ -25,8 +25,14 @@ EXPORTED = [
     "ads_make_rotation", "ads_rotate", "ads_ivf_build", "ads_index_info", "ads_index_lists",
     "ads_index_free", "ads_dco_batch", "ads_search", "ads_search_workspace_size",
     "ads_last_error", "ads_version", "ads_profile_enable", "ads_profile_collect",
+    "ads_set_tuning", "ads_get_tuning",
 ]
 PHASES = ["rotate", "probe", "group", "scan", "merge", "output"]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("dense_frac", ctypes.c_float), ("queries_per_unit", ctypes.c_int32),
+                ("sweep_log2", ctypes.c_int32)]
 
 
 class AdsError(RuntimeError):
@@ -65,13 +71,15 @@ def load() -> ctypes.CDLL:
     lib.ads_search.argtypes = [vp, vp, i32, vp, vp, i32, i32, f32, i32, i32, vp, vp, vp, vp, vp, vp]
     lib.ads_search_workspace_size.argtypes = [vp, i32, i32, i32, i32]
     lib.ads_search_workspace_size.restype = ctypes.c_uint64
+    lib.ads_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
+    lib.ads_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
     lib.ads_profile_enable.argtypes = [i32]
     lib.ads_profile_collect.argtypes = [vp, vp]
     lib.ads_last_error.restype = ctypes.c_char_p
     lib.ads_version.restype = ctypes.c_char_p
     for name in ["ads_make_rotation", "ads_rotate", "ads_ivf_build", "ads_index_info",
                  "ads_index_lists", "ads_index_free", "ads_dco_batch", "ads_search",
-                 "ads_profile_enable", "ads_profile_collect"]:
+                 "ads_profile_enable", "ads_profile_collect", "ads_set_tuning", "ads_get_tuning"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -264,3 +272,22 @@ def profile_collect() -> dict:
     n = np.zeros(len(PHASES), dtype=np.int64)
     _check(load().ads_profile_collect(ms.ctypes.data_as(ctypes.c_void_p), n.ctypes.data_as(ctypes.c_void_p)))
     return {p: (float(ms[i]), int(n[i])) for i, p in enumerate(PHASES)}
+
+
+# ---------------------------------------------------------------------------
+# Scheduling knobs
+# ---------------------------------------------------------------------------
+
+def get_tuning() -> dict:
+    t = Tuning()
+    _check(load().ads_get_tuning(ctypes.byref(t)))
+    return {"dense_frac": t.dense_frac, "queries_per_unit": t.queries_per_unit,
+            "sweep_log2": t.sweep_log2}
+
+
+def set_tuning(dense_frac=None, queries_per_unit=None, sweep_log2=None) -> None:
+    cur = get_tuning()
+    t = Tuning(float(cur["dense_frac"] if dense_frac is None else dense_frac),
+               int(cur["queries_per_unit"] if queries_per_unit is None else queries_per_unit),
+               int(cur["sweep_log2"] if sweep_log2 is None else sweep_log2))
+    _check(load().ads_set_tuning(ctypes.byref(t)))

@@ -17,13 +17,13 @@ __global__ void zero_i32_kernel(int32_t *p, int64_t n);
 __global__ void probe_select_kernel(const float *qrot, const float *dots, const float *cnorm, int D,
                                     int nlist, int nprobe_max, int32_t *probes);
 __global__ void group_count_kernel(const int32_t *probes, const int32_t *npq, const int32_t *keff,
-                                   int nq, int nprobe_max, int nlist, int32_t *cnt);
+                                   int nq, int nprobe_max, int nlist, int lg, int32_t *cnt);
 __global__ void group_scan_kernel(const int32_t *cnt, int nsweep, int nlist, int qw, int32_t *beg,
                                   int32_t *uoff, int32_t *xoff, int32_t *xcnt);
 __global__ void unit_expand_kernel(const int32_t *cnt, const int32_t *beg, const int32_t *uoff, int nsweep,
                                    int nlist, int qw, int64_t ucap, int4 *units);
 __global__ void group_scatter_kernel(const int32_t *probes, const int32_t *npq, const int32_t *keff,
-                                     int nq, int nprobe_max, int nlist, const int32_t *beg,
+                                     int nq, int nprobe_max, int nlist, int lg, const int32_t *beg,
                                      int32_t *cursor, int2 *qent);
 __global__ void merge_kernel(const uint64_t *slots, const int32_t *keff, const int32_t *npq,
                              int nprobe_max, int kcap, int rank_a, int rank_b, uint64_t *tk,
@@ -57,6 +57,7 @@ struct ads_index {
 namespace {
 
 thread_local std::string g_err;
+thread_local ads_tuning g_tune = {0.125f, 0, 3};
 
 // Per-thread event profiler (ads_profile_enable / ads_profile_collect).
 struct Profiler {
@@ -144,14 +145,16 @@ unsigned grid_for(int64_t n, int64_t cap = 65536) {
     return (unsigned)(g > cap ? cap : g);
 }
 
-// Queries per scan unit for a KNN-set capacity (local KNN sets <= 4 KB of LDS).
+// Queries per scan unit for a KNN-set capacity (local KNN sets <= 4 KB of LDS),
+// or the tuned value when it fits.
 int qw_for(int kcap) {
+    int auto_qw = 1;
     for (int qw = 8; qw > 1; qw >>= 1)
-        if (qw * kcap <= 512) return qw;
-    return 1;
+        if (qw * kcap <= 512) { auto_qw = qw; break; }
+    const int t = g_tune.queries_per_unit;
+    if (t > 0 && t * kcap <= 4096) return t;
+    return auto_qw;
 }
-
-constexpr float DENSE_FRAC = 0.5f;
 
 constexpr int KCAP_MAX = 512;
 constexpr int NPROBE_MAX_LIMIT = 8192;
@@ -159,7 +162,7 @@ constexpr int NPROBE_MAX_LIMIT = 8192;
 struct SearchLayout {
     size_t off_qrot, off_dots, off_probes, off_kq, off_keff, off_npq, off_r2, off_tk, off_cnt,
         off_beg, off_cursor, off_uoff, off_xoff, off_xcnt, off_units, off_qent, off_slots, total;
-    int nsweep, kcap, qw;
+    int nsweep, kcap, qw, lg;
     int64_t ucap;
 };
 
@@ -169,7 +172,8 @@ SearchLayout layout_for(const ads_index *ix, int nq, int k_max, int nprobe_max, 
     SearchLayout L{};
     L.kcap = k_max * (rerank ? 4 : 1);
     L.qw = qw_for(L.kcap);
-    L.nsweep = num_sweeps(nprobe_max);
+    L.lg = g_tune.sweep_log2;
+    L.nsweep = num_sweeps(nprobe_max, L.lg);
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + (bytes ? bytes : 1)); return at; };
     const size_t nqs = (size_t)(nq > 0 ? nq : 1);
@@ -584,19 +588,19 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
     {
         PhaseTimer t(ADS_PHASE_GROUP, stream);
         hipLaunchKernelGGL(group_count_kernel, dim3(grid_for((int64_t)nq * nprobe_max)), dim3(ADS_WG), 0, stream,
-                           probes, npq, keff, nq, nprobe_max, nlist, cnt);
+                           probes, npq, keff, nq, nprobe_max, nlist, L.lg, cnt);
         hipLaunchKernelGGL(group_scan_kernel, dim3(1), dim3(1024), 0, stream, cnt, L.nsweep, nlist, qw, beg, uoff,
                            xoff, xcnt);
         hipLaunchKernelGGL(group_scatter_kernel, dim3(grid_for((int64_t)nq * nprobe_max)), dim3(ADS_WG), 0, stream,
-                           probes, npq, keff, nq, nprobe_max, nlist, beg, cursor, qent);
+                           probes, npq, keff, nq, nprobe_max, nlist, L.lg, beg, cursor, qent);
         hipLaunchKernelGGL(unit_expand_kernel, dim3(grid_for(sl)), dim3(ADS_WG), 0, stream, cnt, beg, uoff,
                            L.nsweep, nlist, qw, L.ucap, units);
         SEARCH_TRY(hipGetLastError(), "grouping");
     }
     // 4. sweeps: list-major scan, then per-query merge
     for (int s = 0; s < L.nsweep; ++s) {
-        const int ra = sweep_begin(s);
-        int rb = s + 1 < L.nsweep ? sweep_begin(s + 1) : nprobe_max;
+        const int ra = sweep_begin(s, L.lg);
+        int rb = s + 1 < L.nsweep ? sweep_begin(s + 1, L.lg) : nprobe_max;
         if (rb > nprobe_max) rb = nprobe_max;
         ScanArgs a;
         a.data = ix->data;
@@ -617,12 +621,12 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
         a.kcap = L.kcap;
         a.D = D;
         a.nb = ix->nb;
-        a.dense_frac = DENSE_FRAC;
+        a.dense_frac = g_tune.dense_frac;
         // persistent grid: 8 XCD lanes x P workgroups, P bounded by the units of the sweep
         const int64_t pairs = (int64_t)nq * (rb - ra);
         const int64_t units_bound = (pairs + qw - 1) / qw + (pairs < nlist ? pairs : nlist);
         int64_t P = (units_bound + 7) / 8;
-        if (P > 2048) P = 2048;
+        if (P > 4096) P = 4096;
         if (P < 1) P = 1;
         {
             PhaseTimer t(ADS_PHASE_SCAN, stream);
@@ -654,6 +658,25 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
     }
 #undef SEARCH_TRY
     return done(hipSuccess, "");
+}
+
+extern "C" ads_status ads_set_tuning(const ads_tuning *t) {
+    if (!t) return fail(ADS_EINVAL, "tuning must not be NULL");
+    if (!(t->dense_frac > 0.f && t->dense_frac <= 0.25f))
+        return fail(ADS_EINVAL, "dense_frac must be in (0, 0.25] (got %g)", (double)t->dense_frac);
+    if (t->queries_per_unit != 0 && t->queries_per_unit != 1 && t->queries_per_unit != 2 &&
+        t->queries_per_unit != 4 && t->queries_per_unit != 8 && t->queries_per_unit != 16)
+        return fail(ADS_EINVAL, "queries_per_unit must be 0, 1, 2, 4, 8 or 16 (got %d)", t->queries_per_unit);
+    if (t->sweep_log2 < 1 || t->sweep_log2 > 6)
+        return fail(ADS_EINVAL, "sweep_log2 must be in [1, 6] (got %d)", t->sweep_log2);
+    g_tune = *t;
+    return ADS_OK;
+}
+
+extern "C" ads_status ads_get_tuning(ads_tuning *t) {
+    if (!t) return fail(ADS_EINVAL, "tuning must not be NULL");
+    *t = g_tune;
+    return ADS_OK;
 }
 
 extern "C" ads_status ads_profile_enable(int32_t on) {

@@ -23,13 +23,13 @@ struct ScanArgs {
     double eps0;
     int method;
     int nprobe_max, kcap, D, nb;
-    float dense_frac;       // pairs alive at or below this fraction switch to the pair list
+    float dense_frac;       // pairs alive at or below this fraction (<= 0.5) switch to the pair list
 };
 
 hipError_t launch_scan(const ScanArgs &a, int dtype, int dd, int qw, int grid, hipStream_t s);
 
-int num_sweeps(int nprobe_max);
-int sweep_begin(int s);
+int num_sweeps(int nprobe_max, int lg);
+int sweep_begin(int s, int lg);
 
 hipError_t launch_dco(int dtype, const void *data, const float *rows32, int source,
                       const int64_t *list_off, const int32_t *list_of_pos, const int32_t *pos_of,

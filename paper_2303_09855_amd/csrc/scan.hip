@@ -33,11 +33,11 @@
 
 namespace ads {
 
-constexpr int SCAN_WAVES = 4;    // waves per workgroup; each takes one 64-vector slice per round
+constexpr int SCAN_WAVES = 1;    // waves per workgroup; each takes one 64-vector slice per round
 
 template <int DD, int QW>
 struct ScanSmem {
-    static constexpr int LCAP = 32 * QW;   // pairs alive when the dense phase hands over
+    static constexpr int LCAP = 16 * QW;   // pairs alive when the dense phase hands over (<= 1/4)
     // wave-private
     float qs[SCAN_WAVES][QW][DD + 4];
     uint64_t list[SCAN_WAVES][2][LCAP];
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(64 * SCAN_WAVES) void scan_kernel(ScanArgs a) {
 #pragma unroll
                 for (int jj = 0; jj < QW; ++jj) na += __popcll(__ballot((alive >> jj) & 1u));
                 if (na == 0) break;
-                if (2 * na <= tile_pairs) {
+                if ((float)na <= a.dense_frac * (float)tile_pairs) {
                     uint64_t *list = sm.list[w][0];
                     int base = 0;
 #pragma unroll
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(64 * SCAN_WAVES) void scan_kernel(ScanArgs a) {
                         const bool pv = pi < n;
                         const uint64_t en = pv ? src[pi] : 0ull;
                         const float s0 = __uint_as_float((uint32_t)(en >> 32));
-                        const int jj = (int)(((uint32_t)en >> 6) & 7u), vv = (int)(en & 63u);
+                        const int jj = (int)(((uint32_t)en >> 6) & 31u), vv = (int)(en & 63u);
                         const int blk = bcur + gi;
                         const bool bv = pv && blk < nb;
                         float part = 0.f;
@@ -358,6 +358,7 @@ hipError_t launch_scan_t(const ScanArgs &a, int grid, hipStream_t s) {
 template <int DT, int DD>
 hipError_t launch_scan_q(const ScanArgs &a, int qw, int grid, hipStream_t s) {
     switch (qw) {
+        case 16: return launch_scan_t<DT, DD, 16>(a, grid, s);
         case 8: return launch_scan_t<DT, DD, 8>(a, grid, s);
         case 4: return launch_scan_t<DT, DD, 4>(a, grid, s);
         case 2: return launch_scan_t<DT, DD, 2>(a, grid, s);
@@ -389,14 +390,19 @@ hipError_t launch_scan(const ScanArgs &a, int dtype, int dd, int qw, int grid, h
 // ---------------------------------------------------------------------------
 // Sweep of a probe rank: [0,1) -> 0, [1,4) -> 1, [4,16) -> 2, ...
 // ---------------------------------------------------------------------------
-__host__ __device__ inline int sweep_of(int rank) {
+// With growth g = 2^lg: [0,1) -> 0, [1,g) -> 1, [g,g^2) -> 2, ...
+__host__ __device__ inline int sweep_of(int rank, int lg) {
     if (rank <= 0) return 0;
-    int lg = 31 - __builtin_clz((unsigned)rank);
-    return 1 + (lg >> 1);
+    int l2 = 31 - __builtin_clz((unsigned)rank);
+    return 1 + l2 / lg;
 }
 
-int num_sweeps(int nprobe_max) { return sweep_of(nprobe_max - 1) + 1; }
-int sweep_begin(int s) { return s == 0 ? 0 : 1 << (2 * (s - 1)); }
+int num_sweeps(int nprobe_max, int lg) { return sweep_of(nprobe_max - 1, lg) + 1; }
+int sweep_begin(int s, int lg) {
+    if (s == 0) return 0;
+    const int64_t v = (int64_t)1 << (lg * (s - 1));
+    return v > (1 << 30) ? (1 << 30) : (int)v;
+}
 
 // ---------------------------------------------------------------------------
 // Per-query setup: KNN-set size, probe count, thresholds and KNN sets.
@@ -479,14 +485,14 @@ __global__ __launch_bounds__(ADS_WG) void probe_select_kernel(
 // Grouping of (query, rank) pairs by (sweep, list).
 // ---------------------------------------------------------------------------
 __global__ void group_count_kernel(const int32_t *probes, const int32_t *npq, const int32_t *keff,
-                                   int nq, int nprobe_max, int nlist, int32_t *cnt) {
+                                   int nq, int nprobe_max, int nlist, int lg, int32_t *cnt) {
     int64_t tot = (int64_t)nq * nprobe_max;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot;
          i += (int64_t)gridDim.x * blockDim.x) {
         int q = (int)(i / nprobe_max), rank = (int)(i % nprobe_max);
         if (rank >= npq[q] || keff[q] <= 0) continue;
         int l = probes[i];
-        atomicAdd(&cnt[(int64_t)sweep_of(rank) * nlist + l], 1);
+        atomicAdd(&cnt[(int64_t)sweep_of(rank, lg) * nlist + l], 1);
     }
 }
 
@@ -589,7 +595,7 @@ __global__ void unit_expand_kernel(const int32_t *cnt, const int32_t *beg, const
 }
 
 __global__ void group_scatter_kernel(const int32_t *probes, const int32_t *npq, const int32_t *keff,
-                                     int nq, int nprobe_max, int nlist, const int32_t *beg,
+                                     int nq, int nprobe_max, int nlist, int lg, const int32_t *beg,
                                      int32_t *cursor, int2 *qent) {
     int64_t tot = (int64_t)nq * nprobe_max;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot;
@@ -597,7 +603,7 @@ __global__ void group_scatter_kernel(const int32_t *probes, const int32_t *npq, 
         int q = (int)(i / nprobe_max), rank = (int)(i % nprobe_max);
         if (rank >= npq[q] || keff[q] <= 0) continue;
         int l = probes[i];
-        int64_t slot = (int64_t)sweep_of(rank) * nlist + l;
+        int64_t slot = (int64_t)sweep_of(rank, lg) * nlist + l;
         int p = beg[slot] + atomicAdd(&cursor[slot], 1);
         qent[p] = make_int2(q, rank);
     }
