@@ -175,9 +175,12 @@ ads_status ads_index_free(ads_index *ix);
  *   dist      device [m] float32: dis for positives, +INF for negatives.
  *   dims      device [m] int32 coordinates sampled, or NULL.
  *   stats     device [ADS_NSTATS] int64 accumulators, or NULL.
- * Coordinates are summed in ascending order with one fused multiply-add per
- * coordinate; the test at d < D is  S_d > (d/D)(1+eps0/sqrt(d))^2 r^2  (the
- * squared form of dis' > (1+eps0/sqrt(d)) r); at d = D positive iff S_D <= r^2.
+ * S_d is the sum, in block order, of per-block partial sums over the index's
+ * delta_d-wide blocks (each a chain of fused multiply-adds in ascending
+ * coordinate order) plus the running partial of the current block; the
+ * search uses the same order, so both report identical S.  The test at d < D
+ * is  S_d > (d/D)(1+eps0/sqrt(d))^2 r^2  (the squared form of
+ * dis' > (1+eps0/sqrt(d)) r); at d = D positive iff S_D <= r^2.
  * Errors: ADS_EINVAL (NULL, id out of range, bad parameters), ADS_EHIP.
  */
 ads_status ads_dco_batch(const ads_index *ix, const float *q_rot, const int64_t *cand, int64_t m,

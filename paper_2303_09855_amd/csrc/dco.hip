@@ -29,20 +29,27 @@ __global__ __launch_bounds__(ADS_WG) void dco_kernel(
             const int64_t off = list_off[l];
             const int64_t nl = list_off[l + 1] - off;
             const int64_t v = p - off;
-            float s = 0.f;
+            // canonical order: partial sums of the layout's dd-wide blocks,
+            // each from zero, added in block order (as in the scan kernel)
+            float s_blocks = 0.f, pb = 0.f, s = 0.f;
             int next = step;
             int done = 0;
             int used = D;
             for (int t = 0; t < D; ++t) {
                 float o;
+                const int b = t / dd, k = t - b * dd;
+                if (k == 0 && t > 0) {
+                    s_blocks = s_blocks + pb;
+                    pb = 0.f;
+                }
                 if (source) {
                     o = rows32[p * D + t];
                 } else {
-                    const int b = t / dd, k = t - b * dd;
                     o = load_one<DT>(data, off * D + (int64_t)b * nl * dd + v * dd + k);
                 }
                 float df = o - q[t];
-                s = __fmaf_rn(df, df, s);
+                pb = __fmaf_rn(df, df, pb);
+                s = s_blocks + pb;
                 const int d = t + 1;
                 if (d == next) {
                     next += step;

@@ -162,12 +162,14 @@ __global__ __launch_bounds__(64 * SCAN_WAVES) void scan_kernel(ScanArgs a) {
 #pragma unroll
                     for (int jj = 0; jj < QW; ++jj) {
                         if (!((alive >> jj) & 1u)) continue;
-                        float s = S[jj];
+                        // canonical order: the block's partial from zero, then S += partial
+                        float pb = 0.f;
 #pragma unroll
                         for (int kk = 0; kk < DD; ++kk) {
                             float df = o[kk] - qs[jj][kk];
-                            s = __fmaf_rn(df, df, s);
+                            pb = __fmaf_rn(df, df, pb);
                         }
+                        const float s = S[jj] + pb;
                         S[jj] = s;
                         if (d < D) {
                             if (test_reject(s, cf, sm.r2s[jj])) {
@@ -212,11 +214,13 @@ __global__ __launch_bounds__(64 * SCAN_WAVES) void scan_kernel(ScanArgs a) {
             }
             // sparse phase: all surviving pairs sit at the same next block
             // bcur.  With n pairs left, each pair takes G = 64 / n lanes (a
-            // power of two) that evaluate blocks bcur .. bcur+G-1 at once; a
-            // segmented prefix scan gives S at every block boundary and the
-            // first rejecting block is found with a ballot, so the decisions
-            // are those of testing block by block.  Survivors advance by G
-            // blocks together and are compacted into the other list.
+            // power of two) that evaluate blocks bcur .. bcur+G-1 at once; an
+            // in-group scan gives S at every block boundary and the first
+            // rejecting block is found with a ballot, so the decisions are
+            // those of testing block by block.  Survivors advance by G blocks
+            // together and are compacted into the other list.  S is always
+            // the sum of per-block partials in block order, so a pair's result
+            // does not depend on G or on when it left the dense phase.
             if (sparse) {
                 int bcur = b, cur = 0, n = m;
                 while (n > 0 && bcur < nb) {
@@ -241,12 +245,13 @@ __global__ __launch_bounds__(64 * SCAN_WAVES) void scan_kernel(ScanArgs a) {
                             const unsigned char *op = lbase + ((int64_t)blk * nl * DD + (int64_t)(vc + vv) * DD) * EB;
                             part = block_partial<DT, DD>(op, a.qrot + (int64_t)sm.qidx[jj] * D + blk * DD, 0.f);
                         }
-                        float sc = part;
-                        for (int o = 1; o < G; o <<= 1) {
-                            const float tv = __shfl_up(sc, o, G);
-                            if (gi >= o) sc += tv;
+                        // S after each block, added in block order (the canonical
+                        // order, independent of G): one lane of the group per round
+                        float sb = gi == 0 ? s0 + part : 0.f;
+                        for (int t = 1; t < G; ++t) {
+                            const float prev = __shfl_up(sb, 1, G);
+                            if (gi == t) sb = prev + part;
                         }
-                        const float sb = s0 + sc;
                         const int d = (blk + 1) * DD;
                         const float r2 = pv ? sm.r2s[jj] : 0.f;
                         const bool rej = bv && d < D && test_reject(sb, coef[bv ? blk : 0], r2);

@@ -1,0 +1,209 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py
+times, on sampled queries the oracle recomputes one by one; plus properties
+that hold for every query of the batch (exact returned distances, ascending
+order, returned ids inside the probed lists, DCO count).
+
+Workloads (synthetic stand-ins, see synthdata): ivf_d960 (N = 10^6, D = 960,
+4,096 lists, nprobe 768), ivf_d128 (N = 10^6, D = 128, 10^4 queries, nprobe
+16 / 64, K 10 / 100, float32 and bfloat16 + rerank), batched_d256 (N = 2*10^6,
+D = 256, 8,192 lists, 4,096 queries with per-query nprobe in [8, 128] and K in
+{10, 100})."""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synthdata as sd
+from helpers import tie_band_equal
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+torch = pytest.importorskip("torch")
+
+SAMPLE = 8
+
+
+@pytest.fixture(scope="module")
+def ads():
+    import paper_2303_09855_amd as m
+    m.load()
+    assert torch.cuda.is_available(), "the GPU tests need a visible GPU"
+    return m
+
+
+class Full:
+    """A full-size workload: GPU index plus the oracle's view of sampled queries."""
+
+    def __init__(self, ads, name, storage=0):
+        self.w = w = sd.WORKLOADS[name]
+        self.x = sd.base_vectors(w)
+        self.q = sd.query_vectors(w)
+        self.G = sd.rotation_gaussian(w)
+        self.cent, self.assign = sd.ivf_clustering(w, self.x)
+        P32, _ = ads.make_rotation(self.G)
+        self.ix = ads.ivf_build(self.x, P32, self.cent, self.assign, delta_d=w.delta_d,
+                                storage=storage, keep_fp32=True)
+        self.qd = torch.as_tensor(self.q).cuda()
+        self.P64 = oracle.make_rotation(self.G)
+        self.cr = oracle.rotate(self.cent, self.P64)
+        self.off, self.members = oracle.lists_from_assignment(self.assign, w.nlist)
+        self.sample = np.linspace(0, w.nq - 1, SAMPLE).astype(int)
+        self.qr_s = oracle.rotate(self.q[self.sample], self.P64)
+
+    _xr = None
+
+    def oracle_on_sample(self, probes_s, K, eps0, method, nprobe=None):
+        """IVF scan of the sampled queries by the oracle (FP64 rotation of
+        every base row, done once)."""
+        if self._xr is None:
+            self._xr = np.empty((self.w.n, self.w.D))
+            for s in range(0, self.w.n, 65536):
+                self._xr[s:s + 65536] = oracle.rotate(self.x[s:s + 65536], self.P64)
+        return oracle.ivf_search(self._xr, self.qr_s, self.off, self.members, probes_s, K, eps0,
+                                 self.w.delta_d, method=method, nprobe=nprobe)
+
+    def exact(self, ids, qidx):
+        out = np.full(ids.shape, np.inf)
+        for r, i in enumerate(qidx):
+            v = ids[r] >= 0
+            out[r][v] = oracle.exact_dist(self.x[ids[r][v]], self.q[i])
+        return out
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _every_query_properties(F, ids, dist, probes, npq=None):
+    """Properties that hold at any size, for every query of the batch."""
+    nq = ids.shape[0]
+    ex = F.exact(ids, np.arange(nq))
+    v = ids >= 0
+    assert np.all(np.abs(dist[v] - ex[v]) <= 1e-5 * np.maximum(ex[v], 1e-30)), "returned distances"
+    d = np.where(v, dist, np.inf)
+    assert np.all(np.diff(d, axis=1) >= 0), "ascending order"
+    lst = F.assign[np.where(v, ids, 0)]
+    for i in range(nq):
+        allowed = probes[i][probes[i] >= 0]
+        assert np.all(np.isin(lst[i][v[i]], allowed)), f"query {i}: id outside its probed lists"
+
+
+def _check_sample(F, ids, dist, probes, K, eps0, method, npq=None):
+    s = F.sample
+    pr_o, d2 = oracle.probes(F.qr_s, F.cr, probes.shape[1])
+    same = []
+    for r, i in enumerate(s):
+        n_i = probes.shape[1] if npq is None else int(npq[i])
+        gp = probes[r][:n_i]
+        op = pr_o[r][:n_i]
+        if list(gp) == list(op):
+            same.append(True)
+            continue
+        kth = d2[r][op[-1]]
+        band = set(np.flatnonzero(np.abs(d2[r] - kth) <= 1e-4 * kth).tolist())
+        assert set(gp) - band == set(op) - band, f"query {i}: probe sets differ outside the band"
+        same.append(False)
+    probes_s = np.where(np.arange(probes.shape[1])[None, :] < (
+        probes.shape[1] if npq is None else npq[s][:, None]), probes, -1).astype(np.int32)
+    # the oracle scans the GPU's probe order only when it equals its own
+    o_ids, o_d, o_st = F.oracle_on_sample(pr_o.astype(np.int32), K, eps0, method,
+                                          nprobe=None if npq is None else npq[s])
+    return o_ids, o_d, o_st, np.array(same), probes_s
+
+
+def test_d960_at_bench_operating_point(ads):
+    F = Full(ads, "ivf_d960")
+    nprobe, K = 768, 10
+    stats = torch.zeros(ads.NSTATS, dtype=torch.int64, device="cuda")
+    ids, dist, probes = ads.search(F.ix, F.qd, K, nprobe, eps0=2.1, want_probes=True, stats=stats)
+    ids, dist, probes, st = _np(ids), _np(dist), _np(probes), _np(stats)
+    _every_query_properties(F, ids, dist, probes)
+    lens = np.diff(F.off)
+    assert st[ads.STAT_DCOS] == int(lens[probes].sum())
+    # FDScanning on the sample: ids equal the oracle's outside the tie band
+    f_ids, f_dist, f_probes = ads.search(F.ix, F.qd[F.sample], K, nprobe, eps0=math.inf,
+                                         want_probes=True)
+    f_ids, f_dist, f_probes = _np(f_ids), _np(f_dist), _np(f_probes)
+    o_ids, o_d, _, same, _ = _check_sample(F, f_ids, f_dist, f_probes, K, math.inf,
+                                           oracle.METHOD_FDS)
+    for r in range(SAMPLE):
+        if same[r]:
+            assert tie_band_equal(f_ids[r], f_dist[r], o_ids[r], o_d[r]), r
+    # ADSampling recall on the sample within the parity bar of the oracle's
+    _, gt = oracle.brute_knn(F.x, F.q[F.sample], K)
+    a_ids = ids[F.sample]
+    oa_ids, oa_d, _, _, _ = _check_sample(F, a_ids, dist[F.sample], probes[F.sample], K, 2.1,
+                                          oracle.METHOD_ADS)
+    r_gpu = oracle.recall(a_ids, F.exact(a_ids, F.sample), gt, K)
+    r_orc = oracle.recall(oa_ids, F.exact(oa_ids, F.sample), gt, K)
+    assert abs(r_gpu - r_orc) <= 0.002 + 1.0 / (SAMPLE * K)
+    F.ix.free()
+
+
+_CACHE = {}
+
+
+def _full(ads, name, storage=0):
+    key = (name, storage)
+    if key not in _CACHE:
+        for k in list(_CACHE):
+            _CACHE.pop(k).ix.free()
+        _CACHE[key] = Full(ads, name, storage)
+    return _CACHE[key]
+
+
+@pytest.mark.parametrize("nprobe,K,storage", [(16, 10, 0), (64, 100, 0), (64, 10, 1)])
+def test_d128_full(ads, nprobe, K, storage):
+    F = _full(ads, "ivf_d128", storage=storage)
+    rerank = 1 if storage else 0
+    ids, dist, probes = ads.search(F.ix, F.qd, K, nprobe, eps0=2.1, rerank=rerank,
+                                   want_probes=True)
+    ids, dist, probes = _np(ids), _np(dist), _np(probes)
+    sub = np.arange(0, F.w.nq, 10)          # every 10th query for the per-query properties
+    ex = F.exact(ids[sub], sub)
+    v = ids[sub] >= 0
+    assert np.all(np.abs(dist[sub][v] - ex[v]) <= 1e-5 * np.maximum(ex[v], 1e-30))
+    d = np.where(v, dist[sub], np.inf)
+    assert np.all(np.diff(d, axis=1) >= 0)
+    _, gt = oracle.brute_knn(F.x, F.q[F.sample], K)
+    o_ids, o_d, _, _, _ = _check_sample(F, ids[F.sample], dist[F.sample], probes[F.sample], K,
+                                        2.1, oracle.METHOD_ADS)
+    r_gpu = oracle.recall(ids[F.sample], F.exact(ids[F.sample], F.sample), gt, K)
+    r_orc = oracle.recall(o_ids, F.exact(o_ids, F.sample), gt, K)
+    tol = 0.002 + 1.0 / (SAMPLE * K) + (0.01 if storage else 0.0)
+    assert abs(r_gpu - r_orc) <= tol, (r_gpu, r_orc)
+
+
+def test_batched_uneven_full(ads):
+    F = _full(ads, "batched_d256")
+    Kq, npq = sd.uneven_draws(F.w)
+    k_max, p_max = int(Kq.max()), int(npq.max())
+    ids, dist, probes = ads.search(F.ix, F.qd, k_max, p_max, eps0=2.1, K=Kq, nprobe=npq,
+                                   want_probes=True)
+    ids, dist, probes = _np(ids), _np(dist), _np(probes)
+    sub = np.arange(0, F.w.nq, 16)
+    ex = F.exact(ids[sub], sub)
+    v = ids[sub] >= 0
+    assert np.all(np.abs(dist[sub][v] - ex[v]) <= 1e-5 * np.maximum(ex[v], 1e-30))
+    for r, i in enumerate(sub):
+        assert np.count_nonzero(ids[i] >= 0) <= Kq[i]
+        assert np.all(probes[i][npq[i]:] == -1)
+    # the sample against the oracle with the same per-query K and nprobe
+    _, gt = oracle.brute_knn(F.x, F.q[F.sample], k_max)
+    Ks = Kq[F.sample]
+    pr_o, _ = oracle.probes(F.qr_s, F.cr, p_max)
+    o_ids, o_d, _ = F.oracle_on_sample(pr_o.astype(np.int32), Ks, 2.1, oracle.METHOD_ADS,
+                                       nprobe=npq[F.sample])
+    g = ids[F.sample]
+    r_gpu = oracle.recall(g, F.exact(g, F.sample), gt, Ks)
+    r_orc = oracle.recall(o_ids, F.exact(o_ids, F.sample), gt, Ks)
+    assert abs(r_gpu - r_orc) <= 0.002 + 1.0 / int(Ks.sum())
+    # each sampled query alone gives bit-identical results
+    for i in F.sample[:4]:
+        a_ids, a_d = ads.search(F.ix, F.qd[i:i + 1], int(Kq[i]), int(npq[i]), eps0=2.1)
+        assert np.array_equal(_np(a_ids)[0], ids[i, :Kq[i]])
+        assert np.array_equal(_np(a_d)[0], dist[i, :Kq[i]])
+    _CACHE.pop(("batched_d256", 0)).ix.free()

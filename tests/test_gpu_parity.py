@@ -245,3 +245,20 @@ def test_low_precision_storage_with_rerank(ads, ivf960, storage):
         errs.extend((np.abs(dist[i][v] - ex) / ex).tolist())
     assert max(errs) <= 1e-5
     assert oracle.recall(ids, ex_all, gt, K) >= oracle.recall(o_ids, w.exact(o_ids), gt, K) - 0.01
+
+
+def test_search_distances_equal_dco_batch(ads, ivf960):
+    """The scan and the explicit-candidate DCO sum a pair in the same canonical
+    order (per-block partials added in block order), so a returned distance
+    equals dco_batch's distance for the same pair bit for bit (IVF+ == IVF++,
+    Section 5.2), whatever phase of the scan finished the pair."""
+    w, ix = ivf960
+    P32, _ = ads.make_rotation(w.G)
+    qr = ads.rotate(P32, w.q)
+    for eps0 in (math.inf, 2.1):
+        ids, dist = ads.search(ix, w.q, 10, 6, eps0=eps0)
+        ids, dist = _np(ids), _np(dist)
+        for i in range(0, w.nq, 7):
+            v = ids[i] >= 0
+            m, d, _ = ads.dco_batch(ix, qr[i], ids[i][v], math.inf, math.inf, 32)
+            assert np.array_equal(_np(d), dist[i][v])
