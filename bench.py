@@ -57,6 +57,13 @@ def parse():
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fds", action="store_true")
+    ap.add_argument("--mode", default="search", choices=["search", "serve"],
+                    help="search: the throughput benchmark (default); serve: the continuous-"
+                         "batching request loop at Poisson arrival rates")
+    ap.add_argument("--rates", default="5000,20000,50000", help="serve mode: arrivals per second")
+    ap.add_argument("--serve-requests", type=int, default=20000, help="serve mode: requests per rate")
+    ap.add_argument("--serve-nprobe", default="32,64",
+                    help="serve mode: per-request nprobe drawn uniformly from this list")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device-to-device copy first (reference kernel "
                          "of known size for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -176,6 +183,9 @@ def main() -> int:
             f"scan {ph['scan'][0] / args.steps:.3f} ms/step")
         return ms, st, ph
 
+    if args.mode == "serve":
+        return serve(args, w, ix, q, gt, x)
+
     p_ads, r_ads = operating_point(args.eps0, "ADSampling")
     ms_ads, st_ads, ph_ads = timed(p_ads, args.eps0, "ADSampling")
     fds = None
@@ -245,6 +255,44 @@ def main() -> int:
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    ix.free()
+    return 0
+
+
+def serve(args, w, ix, q, gt, x):
+    """Continuous-batching loop at each arrival rate; one JSON line."""
+    import oracle
+    import synthdata as sd
+    from paper_2303_09855_amd.serving import Request, Server
+    rng = np.random.default_rng(1048)
+    nps = [int(v) for v in args.serve_nprobe.split(",")]
+    out = []
+    for rate in [float(v) for v in args.rates.split(",")]:
+        n = args.serve_requests
+        t = sd.poisson_arrivals(rate, n, seed=1047)
+        qi = np.arange(n) % w.nq
+        Ks = rng.choice([10, 100], size=n)
+        Ps = rng.choice(nps, size=n)
+        reqs = [Request(i, q[qi[i]], int(Ks[i]), int(Ps[i]), float(t[i])) for i in range(n)]
+        srv = Server(ix, k_max=100, nprobe_max=max(nps), eps0=args.eps0, max_batch=512, n_streams=3)
+        res, lat, st = srv.run(reqs)
+        # recall@10 of the first 10 results of every request against the exact top-10
+        ids = np.stack([np.pad(res[i][0][:10], (0, max(0, 10 - len(res[i][0][:10]))),
+                               constant_values=-1) for i in range(n)])
+        rec = oracle.recall(ids, np.stack([exact_for(x, q[qi[i]:qi[i] + 1], ids[i:i + 1])[0]
+                                           for i in range(n)]), gt[qi], 10)
+        log(f"serve rate {rate:.0f}/s: {st['qps']:.0f} QPS, p50 {st['p50_ms']:.2f} ms, "
+            f"p99 {st['p99_ms']:.2f} ms, {st['batches']} batches, recall@10 {rec:.4f}")
+        out.append({"rate": rate, "qps": round(st["qps"], 1), "p50_ms": round(st["p50_ms"], 3),
+                    "p99_ms": round(st["p99_ms"], 3), "batches": st["batches"],
+                    "recall_at_10": round(rec, 4)})
+    line = {"metric": "serving latency at Poisson arrival rates (p50/p99) and QPS",
+            "value": out[-1]["qps"], "unit": "queries/s", "n_gpus": 1, "higher_is_better": True,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"{w.name} index, requests cycle its {w.nq} queries, "
+                                   f"K in {{10,100}}, nprobe in {nps}, batches <= 512, 3 streams"},
+            "rates": out}
+    print(json.dumps(line), flush=True)
     ix.free()
     return 0
 

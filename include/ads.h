@@ -228,6 +228,36 @@ uint64_t ads_search_workspace_size(const ads_index *ix, int32_t nq, int32_t k_ma
                                    int32_t nprobe_max, int32_t rerank);
 
 /* --------------------------------------------------------------------------
+ * Captured searches: one graph launch per batch.
+ * -------------------------------------------------------------------------- */
+
+/* Opaque captured search: the whole ads_search launch sequence recorded once
+ * into a HIP graph for fixed buffers and sizes. */
+typedef struct ads_plan ads_plan;
+
+/*
+ * ads_plan_create -- records ads_search(ix, q, nq, K, nprobe, k_max,
+ * nprobe_max, eps0, method, rerank, ids, dist, NULL, NULL, workspace) on
+ * `stream` with stream capture and instantiates the graph.  Nothing runs at
+ * creation.  Every pointer is bound into the plan: before each launch the
+ * caller rewrites the contents of q (and K / nprobe, which may differ per
+ * query and per launch) at the same addresses.  `workspace` is required (the
+ * graph must not allocate).  The plan uses the tuning of the calling thread at
+ * creation.  Errors: as ads_search, plus ADS_EINVAL for a NULL workspace and
+ * ADS_EHIP if the stream cannot be captured (e.g. the legacy null stream).
+ */
+ads_status ads_plan_create(const ads_index *ix, const float *q, int32_t nq, const int32_t *K,
+                           const int32_t *nprobe, int32_t k_max, int32_t nprobe_max, float eps0,
+                           int32_t method, int32_t rerank, int64_t *ids, float *dist,
+                           void *workspace, hipStream_t stream, ads_plan **out);
+
+/* ads_plan_launch -- replays the captured search on `stream` (one graph launch). */
+ads_status ads_plan_launch(ads_plan *plan, hipStream_t stream);
+
+/* ads_plan_free -- destroys the plan (synchronises the device).  NULL is a no-op. */
+ads_status ads_plan_free(ads_plan *plan);
+
+/* --------------------------------------------------------------------------
  * Scheduling knobs of the scan (no effect on what a DCO decides).
  * -------------------------------------------------------------------------- */
 
@@ -239,6 +269,8 @@ typedef struct {
                                  1..8 whose KNN sets fit in 4 KB of LDS.  Default 0. */
     int32_t sweep_log2;       /* probe ranks are scanned in sweeps [0,1), [1,g), [g,g^2), ...
                                  with g = 2^sweep_log2, sweep_log2 in [1, 6].  Default 3. */
+    int32_t grid_per_xcd;     /* persistent scan workgroups per XCD, 0 = as many as the
+                                 sweep has units (capped at 4096).  Default 0. */
 } ads_tuning;
 
 /* ads_set_tuning / ads_get_tuning -- HOST, per thread: knobs for later

@@ -25,14 +25,14 @@ EXPORTED = [
     "ads_make_rotation", "ads_rotate", "ads_ivf_build", "ads_index_info", "ads_index_lists",
     "ads_index_free", "ads_dco_batch", "ads_search", "ads_search_workspace_size",
     "ads_last_error", "ads_version", "ads_profile_enable", "ads_profile_collect",
-    "ads_set_tuning", "ads_get_tuning",
+    "ads_set_tuning", "ads_get_tuning", "ads_plan_create", "ads_plan_launch", "ads_plan_free",
 ]
 PHASES = ["rotate", "probe", "group", "scan", "merge", "output"]
 
 
 class Tuning(ctypes.Structure):
     _fields_ = [("dense_frac", ctypes.c_float), ("queries_per_unit", ctypes.c_int32),
-                ("sweep_log2", ctypes.c_int32)]
+                ("sweep_log2", ctypes.c_int32), ("grid_per_xcd", ctypes.c_int32)]
 
 
 class AdsError(RuntimeError):
@@ -71,6 +71,10 @@ def load() -> ctypes.CDLL:
     lib.ads_search.argtypes = [vp, vp, i32, vp, vp, i32, i32, f32, i32, i32, vp, vp, vp, vp, vp, vp]
     lib.ads_search_workspace_size.argtypes = [vp, i32, i32, i32, i32]
     lib.ads_search_workspace_size.restype = ctypes.c_uint64
+    lib.ads_plan_create.argtypes = [vp, vp, i32, vp, vp, i32, i32, f32, i32, i32, vp, vp, vp, vp,
+                                    ctypes.POINTER(vp)]
+    lib.ads_plan_launch.argtypes = [vp, vp]
+    lib.ads_plan_free.argtypes = [vp]
     lib.ads_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
     lib.ads_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
     lib.ads_profile_enable.argtypes = [i32]
@@ -79,7 +83,8 @@ def load() -> ctypes.CDLL:
     lib.ads_version.restype = ctypes.c_char_p
     for name in ["ads_make_rotation", "ads_rotate", "ads_ivf_build", "ads_index_info",
                  "ads_index_lists", "ads_index_free", "ads_dco_batch", "ads_search",
-                 "ads_profile_enable", "ads_profile_collect", "ads_set_tuning", "ads_get_tuning"]:
+                 "ads_profile_enable", "ads_profile_collect", "ads_set_tuning", "ads_get_tuning",
+                 "ads_plan_create", "ads_plan_launch", "ads_plan_free"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -281,13 +286,68 @@ def profile_collect() -> dict:
 def get_tuning() -> dict:
     t = Tuning()
     _check(load().ads_get_tuning(ctypes.byref(t)))
-    return {"dense_frac": t.dense_frac, "queries_per_unit": t.queries_per_unit,
-            "sweep_log2": t.sweep_log2}
+    return {f: getattr(t, f) for f, _ in Tuning._fields_}
 
 
-def set_tuning(dense_frac=None, queries_per_unit=None, sweep_log2=None) -> None:
+def set_tuning(**kw) -> None:
+    """Update the calling thread's scan knobs (dense_frac, queries_per_unit,
+    sweep_log2, grid_per_xcd); unspecified ones keep their value."""
     cur = get_tuning()
-    t = Tuning(float(cur["dense_frac"] if dense_frac is None else dense_frac),
-               int(cur["queries_per_unit"] if queries_per_unit is None else queries_per_unit),
-               int(cur["sweep_log2"] if sweep_log2 is None else sweep_log2))
+    unknown = set(kw) - set(cur)
+    if unknown:
+        raise ValueError(f"unknown tuning fields {sorted(unknown)}")
+    cur.update({k: v for k, v in kw.items() if v is not None})
+    t = Tuning(float(cur["dense_frac"]), int(cur["queries_per_unit"]), int(cur["sweep_log2"]),
+               int(cur["grid_per_xcd"]))
     _check(load().ads_set_tuning(ctypes.byref(t)))
+
+
+# ---------------------------------------------------------------------------
+# Captured searches (one HIP graph launch per batch)
+# ---------------------------------------------------------------------------
+
+class Plan:
+    """A search recorded into a HIP graph for fixed buffers.
+
+    Write new queries into ``plan.q`` (and per-query ``plan.K`` / ``plan.nprobe``)
+    in place, call ``launch()``, read ``plan.ids`` / ``plan.dist``."""
+
+    def __init__(self, index: Index, nq: int, k_max: int, nprobe_max: int, eps0: float = 2.1,
+                 method: int = ADSAMPLING, rerank: int = 0, stream=None):
+        torch = _torch()
+        self.index = index
+        D = index.info()["D"]
+        self.q = torch.zeros((nq, D), dtype=torch.float32, device="cuda")
+        self.K = torch.full((nq,), k_max, dtype=torch.int32, device="cuda")
+        self.nprobe = torch.full((nq,), nprobe_max, dtype=torch.int32, device="cuda")
+        self.ids = torch.empty((nq, k_max), dtype=torch.int64, device="cuda")
+        self.dist = torch.empty((nq, k_max), dtype=torch.float32, device="cuda")
+        ws = search_workspace_size(index, nq, k_max, nprobe_max, rerank)
+        self.workspace = torch.empty(ws + 256, dtype=torch.uint8, device="cuda")
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws_ptr = ctypes.c_void_p(self.workspace.data_ptr() + off)
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        torch.cuda.synchronize()
+        h = ctypes.c_void_p()
+        e = math.inf if eps0 is None else float(eps0)
+        _check(load().ads_plan_create(index.handle, _ptr(self.q), nq, _ptr(self.K), _ptr(self.nprobe),
+                                      int(k_max), int(nprobe_max), e, int(method), int(rerank),
+                                      _ptr(self.ids), _ptr(self.dist), self._ws_ptr,
+                                      ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None) -> None:
+        torch = _torch()
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(load().ads_plan_launch(self._h, ctypes.c_void_p(s.cuda_stream)))
+
+    def free(self) -> None:
+        if self._h:
+            load().ads_plan_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -57,7 +57,7 @@ struct ads_index {
 namespace {
 
 thread_local std::string g_err;
-thread_local ads_tuning g_tune = {0.125f, 0, 3};
+thread_local ads_tuning g_tune = {0.125f, 0, 3, 0};
 
 // Per-thread event profiler (ads_profile_enable / ads_profile_collect).
 struct Profiler {
@@ -84,7 +84,10 @@ struct PhaseTimer {
     int phase;
     hipEvent_t a = nullptr;
     PhaseTimer(int ph, hipStream_t st) : s(st), phase(ph) {
-        if (g_prof.on && (a = g_prof.get())) (void)hipEventRecord(a, s);
+        if (!g_prof.on) return;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+        if ((a = g_prof.get())) (void)hipEventRecord(a, s);
     }
     ~PhaseTimer() {
         if (!a) return;
@@ -627,6 +630,7 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
         const int64_t units_bound = (pairs + qw - 1) / qw + (pairs < nlist ? pairs : nlist);
         int64_t P = (units_bound + 7) / 8;
         if (P > 4096) P = 4096;
+        if (g_tune.grid_per_xcd > 0 && P > g_tune.grid_per_xcd) P = g_tune.grid_per_xcd;
         if (P < 1) P = 1;
         {
             PhaseTimer t(ADS_PHASE_SCAN, stream);
@@ -660,6 +664,70 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
     return done(hipSuccess, "");
 }
 
+struct ads_plan {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" ads_status ads_plan_create(const ads_index *ix, const float *q, int32_t nq, const int32_t *K,
+                                      const int32_t *nprobe, int32_t k_max, int32_t nprobe_max, float eps0,
+                                      int32_t method, int32_t rerank, int64_t *ids, float *dist,
+                                      void *workspace, hipStream_t stream, ads_plan **out) {
+    if (!out) return fail(ADS_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    if (!workspace) return fail(ADS_EINVAL, "a captured search needs a caller workspace");
+    ads_status st = check_search_args(ix, nq, k_max, nprobe_max, rerank);
+    if (st != ADS_OK) return st;
+    if (nq < 1) return fail(ADS_EINVAL, "nq must be >= 1 for a plan");
+    if (!q || !ids || !dist) return fail(ADS_EINVAL, "q, ids and dist must not be NULL");
+    HIP_TRY(hipGetLastError(), "pending HIP error");
+    ads_plan *p = new (std::nothrow) ads_plan();
+    if (!p) return fail(ADS_ENOMEM, "host allocation failed");
+    hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "begin capture");
+    }
+    st = ads_search(ix, q, nq, K, nprobe, k_max, nprobe_max, eps0, method, rerank, ids, dist, nullptr,
+                    nullptr, workspace, stream);
+    std::string msg = g_err;
+    e = hipStreamEndCapture(stream, &p->graph);
+    if (st != ADS_OK) {
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        delete p;
+        g_err = msg;
+        return st;
+    }
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "end capture");
+    }
+    e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(p->graph);
+        delete p;
+        return hip_fail(e, "instantiate graph");
+    }
+    *out = p;
+    return ADS_OK;
+}
+
+extern "C" ads_status ads_plan_launch(ads_plan *plan, hipStream_t stream) {
+    if (!plan || !plan->exec) return fail(ADS_EINVAL, "plan is NULL");
+    HIP_TRY(hipGetLastError(), "pending HIP error");
+    HIP_TRY(hipGraphLaunch(plan->exec, stream), "graph launch");
+    return ADS_OK;
+}
+
+extern "C" ads_status ads_plan_free(ads_plan *plan) {
+    if (!plan) return ADS_OK;
+    (void)hipDeviceSynchronize();
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    delete plan;
+    return ADS_OK;
+}
+
 extern "C" ads_status ads_set_tuning(const ads_tuning *t) {
     if (!t) return fail(ADS_EINVAL, "tuning must not be NULL");
     if (!(t->dense_frac > 0.f && t->dense_frac <= 0.25f))
@@ -669,6 +737,8 @@ extern "C" ads_status ads_set_tuning(const ads_tuning *t) {
         return fail(ADS_EINVAL, "queries_per_unit must be 0, 1, 2, 4, 8 or 16 (got %d)", t->queries_per_unit);
     if (t->sweep_log2 < 1 || t->sweep_log2 > 6)
         return fail(ADS_EINVAL, "sweep_log2 must be in [1, 6] (got %d)", t->sweep_log2);
+    if (t->grid_per_xcd < 0 || t->grid_per_xcd > 65536)
+        return fail(ADS_EINVAL, "grid_per_xcd must be in [0, 65536] (got %d)", t->grid_per_xcd);
     g_tune = *t;
     return ADS_OK;
 }
