@@ -54,6 +54,13 @@ typedef enum {
     ADS_METHOD_PDSCANNING = 2   /* partial-distance early stop on raw coordinates (Section 6.1) */
 } ads_method;
 
+typedef enum {
+    ADS_METRIC_L2 = 0,      /* Euclidean distance (the paper's setting) */
+    ADS_METRIC_COSINE = 1   /* cosine: base vectors, centres and queries are normalised to unit
+                               length, then searched in L2 (Section 7: cosine search equals
+                               Euclidean search on normalised vectors) */
+} ads_metric;
+
 /* Opaque index.  Device-resident, owned by the library, read-only after
  * ads_ivf_build returns, released by ads_index_free. */
 typedef struct ads_index ads_index;
@@ -67,6 +74,7 @@ typedef struct {
     int32_t storage;        /* ads_dtype of the blocked layout */
     int32_t has_fp32_copy;  /* 1 if a float32 row copy is kept (rerank / dco source) */
     int32_t max_list;       /* largest list size */
+    int32_t metric;         /* ads_metric */
     int64_t device_bytes;   /* device memory held by the index */
 } ads_index_desc;
 
@@ -125,6 +133,11 @@ ads_status ads_rotate(const float *P, int32_t D, const float *X, int64_t n, floa
  *   storage    ads_dtype of the blocked layout.
  *   keep_fp32  1 to keep a float32 copy of the rotated rows (required by the
  *              low-precision rerank and by ads_dco_batch's row source).
+ *   metric     ads_metric.  ADS_METRIC_COSINE normalises every base vector and
+ *              centre before rotating (a zero vector stays zero) and keeps the
+ *              raw norms for ads_dco_batch_ip; searches then normalise their
+ *              queries and report distances between unit vectors
+ *              (cosine similarity = 1 - dist^2 / 2).
  *   out        host pointer receiving the new index.
  * Layout: the rotated vectors of list l are stored as [block][vector][delta_d]
  * (all vectors' first block contiguous, then the second block, ...): the
@@ -135,7 +148,7 @@ ads_status ads_rotate(const float *P, int32_t D, const float *X, int64_t n, floa
  */
 ads_status ads_ivf_build(const float *base, int64_t n, int32_t D, const float *P,
                          const float *centroids, int32_t nlist, const int32_t *assign,
-                         int32_t delta_d, int32_t storage, int32_t keep_fp32,
+                         int32_t delta_d, int32_t storage, int32_t keep_fp32, int32_t metric,
                          hipStream_t stream, ads_index **out);
 
 /* ads_index_info -- HOST: fills *info (host pointer).  ADS_EINVAL on NULL. */
@@ -187,6 +200,25 @@ ads_status ads_dco_batch(const ads_index *ix, const float *q_rot, const int64_t 
                          float r, float eps0, int32_t delta_d, int32_t method, int32_t source,
                          uint8_t *pos_mask, float *dist, int32_t *dims, int64_t *stats,
                          hipStream_t stream);
+
+/*
+ * ads_dco_batch_ip -- inner-product comparison <o, q> >= r for explicit
+ * candidates, reduced to a DCO on unit vectors (Section 7, extension (1)):
+ * <o,q> >= r  <=>  || o/|o| - q/|q| || <= sqrt(2 - 2 r / (|o| |q|)), decided by
+ * Algorithm 1 (or FDScanning / PDScanning) with that per-candidate threshold.
+ * Needs an index built with ADS_METRIC_COSINE (it keeps the raw norms).
+ *   q        device [D] float32 RAW query (normalised and rotated inside).
+ *   r        inner-product threshold (any finite value).
+ *   ip       device [m] float32: <o, q> = |o||q|(1 - d^2/2) for positives,
+ *            -INF for negatives (d: distance of the unit vectors).
+ *   Other arguments as ads_dco_batch (source 0 only).  A candidate whose
+ *   threshold is negative under the root can never reach r: negative with 0
+ *   dims.  If |o||q| = 0, positive iff r <= 0.  Allocates D * 8 bytes of
+ *   stream-ordered scratch.
+ */
+ads_status ads_dco_batch_ip(const ads_index *ix, const float *q, const int64_t *cand, int64_t m,
+                            float r, float eps0, int32_t delta_d, int32_t method, uint8_t *pos_mask,
+                            float *ip, int32_t *dims, int64_t *stats, hipStream_t stream);
 
 /*
  * ads_search -- IVF+ / IVF++ KNN search (Section 2.2.2 with ADSampling as the

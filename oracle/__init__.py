@@ -16,6 +16,8 @@ What it computes, each function citing the passage it follows:
   (Section 2.2.2);
 * :func:`dco_batch` -- Definition 2.1 by FDScanning, Algorithm 1
   (ADSampling) or PDScanning (Section 6.1) for a fixed threshold;
+* :func:`ip_dco_batch` / :func:`normalize` -- Section 7's reduction of cosine
+  search and inner-product comparisons to DCOs on unit vectors;
 * :func:`ivf_search` -- the IVF scan with a KNN max-heap (Section 2.2.2), with
   ADSampling as its DCO (IVF+, Section 4).  IVF++ (Section 5.2) changes only the
   memory layout and gives the same result, so one oracle covers both;
@@ -261,6 +263,55 @@ def dco_batch(base_rot: np.ndarray, q_rot: np.ndarray, rows: np.ndarray, r: floa
                       int(method), _p(mask, ctypes.c_uint8), _p(dist, ctypes.c_double),
                       _p(dims, ctypes.c_int32), _p(band, ctypes.c_uint8), float(band_rel))
     return {"mask": mask, "dist": dist, "dims": dims, "band": band}
+
+
+# ---------------------------------------------------------------------------
+# Section 7, extension (1): cosine similarity and inner product
+# ---------------------------------------------------------------------------
+
+
+def normalize(x: np.ndarray) -> np.ndarray:
+    """Rows scaled to unit length (a zero row stays zero), float64."""
+    x = np.asarray(x, dtype=np.float64)
+    n = np.linalg.norm(x, axis=1, keepdims=True)
+    return np.divide(x, n, out=np.zeros_like(x), where=n > 0)
+
+
+def ip_dco_batch(base_raw: np.ndarray, q_raw: np.ndarray, rows: np.ndarray, r: float,
+                 P64: np.ndarray, eps0: float, delta_d: int, method: int = METHOD_ADS,
+                 band_rel: float = 1e-5):
+    """<o, q> >= r decided as a DCO on unit vectors (Section 7): the
+    comparison holds iff || o/|o| - q/|q| || <= sqrt(2 - 2 r / (|o| |q|)).
+
+    Returns dict(mask, ip (<o,q> for positives, -inf otherwise), dims, band)."""
+    base = np.asarray(base_raw, dtype=np.float64)[np.asarray(rows, dtype=np.int64)]
+    q = np.asarray(q_raw, dtype=np.float64)
+    no = np.linalg.norm(base, axis=1)
+    nq = float(np.linalg.norm(q))
+    bu = rotate(normalize(base), P64)
+    qu = rotate(normalize(q[None, :]), P64)[0]
+    m = len(rows)
+    mask = np.zeros(m, dtype=np.uint8)
+    ip = np.full(m, -np.inf)
+    dims = np.zeros(m, dtype=np.int32)
+    band = np.zeros(m, dtype=np.uint8)
+    for i in range(m):
+        nn = no[i] * nq
+        if nn == 0.0:
+            mask[i] = 1 if r <= 0 else 0
+            ip[i] = 0.0 if mask[i] else -np.inf
+            continue
+        t = 2.0 - 2.0 * r / nn
+        if t < 0.0:
+            continue
+        res = dco_batch(bu[i:i + 1], qu, np.array([0]), np.sqrt(t), eps0, delta_d, method, band_rel)
+        mask[i] = res["mask"][0]
+        dims[i] = res["dims"][0]
+        band[i] = res["band"][0]
+        if mask[i]:
+            d = res["dist"][0]
+            ip[i] = nn * (1.0 - 0.5 * d * d)
+    return {"mask": mask, "ip": ip, "dims": dims, "band": band}
 
 
 # ---------------------------------------------------------------------------

@@ -9,5 +9,5 @@ from ._binding import (  # noqa: F401
     ADSAMPLING, BF16, EXPORTED, F16, F32, FDSCANNING, NSTATS, PDSCANNING, STAT_BYTES, STAT_DCOS,
     STAT_DIMS, STAT_POSITIVES, AdsError, Index, dco_batch, ivf_build, last_error, load,
     make_rotation, profile_collect, profile_enable, rotate, search, search_workspace_size, version,
-    PHASES, Plan, get_tuning, set_tuning,
+    PHASES, METRIC_COSINE, METRIC_L2, Plan, dco_batch_ip, get_tuning, set_tuning,
 )

@@ -26,7 +26,9 @@ EXPORTED = [
     "ads_index_free", "ads_dco_batch", "ads_search", "ads_search_workspace_size",
     "ads_last_error", "ads_version", "ads_profile_enable", "ads_profile_collect",
     "ads_set_tuning", "ads_get_tuning", "ads_plan_create", "ads_plan_launch", "ads_plan_free",
+    "ads_dco_batch_ip",
 ]
+METRIC_L2, METRIC_COSINE = 0, 1
 PHASES = ["rotate", "probe", "group", "scan", "merge", "output"]
 
 
@@ -45,7 +47,7 @@ class IndexDesc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("D", ctypes.c_int32), ("nlist", ctypes.c_int32),
                 ("delta_d", ctypes.c_int32), ("storage", ctypes.c_int32),
                 ("has_fp32_copy", ctypes.c_int32), ("max_list", ctypes.c_int32),
-                ("device_bytes", ctypes.c_int64)]
+                ("metric", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
 
 
 _lib = None
@@ -62,8 +64,9 @@ def load() -> ctypes.CDLL:
     vp, i32, i64, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
     lib.ads_make_rotation.argtypes = [vp, i32, vp, vp]
     lib.ads_rotate.argtypes = [vp, i32, vp, i64, vp, vp]
-    lib.ads_ivf_build.argtypes = [vp, i64, i32, vp, vp, i32, vp, i32, i32, i32, vp,
+    lib.ads_ivf_build.argtypes = [vp, i64, i32, vp, vp, i32, vp, i32, i32, i32, i32, vp,
                                   ctypes.POINTER(vp)]
+    lib.ads_dco_batch_ip.argtypes = [vp, vp, vp, i64, f32, f32, i32, i32, vp, vp, vp, vp, vp]
     lib.ads_index_info.argtypes = [vp, ctypes.POINTER(IndexDesc)]
     lib.ads_index_lists.argtypes = [vp, vp, vp, vp, vp]
     lib.ads_index_free.argtypes = [vp]
@@ -84,7 +87,7 @@ def load() -> ctypes.CDLL:
     for name in ["ads_make_rotation", "ads_rotate", "ads_ivf_build", "ads_index_info",
                  "ads_index_lists", "ads_index_free", "ads_dco_batch", "ads_search",
                  "ads_profile_enable", "ads_profile_collect", "ads_set_tuning", "ads_get_tuning",
-                 "ads_plan_create", "ads_plan_launch", "ads_plan_free"]:
+                 "ads_plan_create", "ads_plan_launch", "ads_plan_free", "ads_dco_batch_ip"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -198,7 +201,7 @@ class Index:
 
 
 def ivf_build(base, P, centroids, assign, delta_d: int = 32, storage: int = F32,
-              keep_fp32: bool = True) -> Index:
+              keep_fp32: bool = True, metric: int = METRIC_L2) -> Index:
     torch = _torch()
     base = _dev(base, torch.float32)
     P = _dev(P, torch.float32)
@@ -208,7 +211,7 @@ def ivf_build(base, P, centroids, assign, delta_d: int = 32, storage: int = F32,
     out = ctypes.c_void_p()
     _check(load().ads_ivf_build(_ptr(base), n, D, _ptr(P), _ptr(centroids), centroids.shape[0],
                                 _ptr(assign), int(delta_d), int(storage), int(bool(keep_fp32)),
-                                _stream(), ctypes.byref(out)))
+                                int(metric), _stream(), ctypes.byref(out)))
     return Index(out)
 
 
@@ -230,6 +233,23 @@ def dco_batch(index: Index, q_rot, cand, r: float, eps0: float, delta_d: int,
                                 int(delta_d), int(method), int(source), _ptr(mask), _ptr(dist),
                                 _ptr(dims), _ptr(stats), _stream()))
     return mask, dist, dims
+
+
+def dco_batch_ip(index: Index, q, cand, r: float, eps0: float, delta_d: int,
+                 method: int = ADSAMPLING, stats=None):
+    """Inner-product comparisons <o,q> >= r on a cosine index (q raw).
+    Returns (mask uint8, ip float32 (-inf for negatives), dims int32)."""
+    torch = _torch()
+    q = _dev(q, torch.float32).reshape(-1)
+    cand = _dev(cand, torch.int64).reshape(-1)
+    m = cand.shape[0]
+    mask = torch.empty(m, dtype=torch.uint8, device="cuda")
+    ip = torch.empty(m, dtype=torch.float32, device="cuda")
+    dims = torch.empty(m, dtype=torch.int32, device="cuda")
+    _check(load().ads_dco_batch_ip(index.handle, _ptr(q), _ptr(cand), m, float(r), float(eps0),
+                                   int(delta_d), int(method), _ptr(mask), _ptr(ip), _ptr(dims),
+                                   _ptr(stats), _stream()))
+    return mask, ip, dims
 
 
 def search_workspace_size(index: Index, nq: int, k_max: int, nprobe_max: int, rerank: int = 0) -> int:

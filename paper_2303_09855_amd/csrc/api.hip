@@ -41,7 +41,8 @@ using namespace ads;
 
 struct ads_index {
     int64_t n = 0;
-    int D = 0, nlist = 0, dd = 0, nb = 0, storage = 0, keep_fp32 = 0, max_list = 0;
+    int D = 0, nlist = 0, dd = 0, nb = 0, storage = 0, keep_fp32 = 0, max_list = 0, metric = 0;
+    float *norms = nullptr;      // [n] raw norms by id (cosine indexes)
     float *P = nullptr;          // [D][D]
     float *cent_rot = nullptr;   // [nlist][D]
     float *cent_norm = nullptr;  // [nlist]
@@ -126,7 +127,7 @@ bool valid_dd(int dd) { return dd == 8 || dd == 16 || dd == 32 || dd == 64; }
 void free_index(ads_index *ix) {
     if (!ix) return;
     void *ptrs[] = {ix->P, ix->cent_rot, ix->cent_norm, ix->list_off, ix->ids, ix->pos_of,
-                    ix->list_of_pos, ix->data, ix->rows32};
+                    ix->list_of_pos, ix->data, ix->rows32, ix->norms};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete ix;
@@ -163,7 +164,7 @@ constexpr int KCAP_MAX = 512;
 constexpr int NPROBE_MAX_LIMIT = 8192;
 
 struct SearchLayout {
-    size_t off_qrot, off_dots, off_probes, off_kq, off_keff, off_npq, off_r2, off_tk, off_cnt,
+    size_t off_qrot, off_qunit, off_dots, off_probes, off_kq, off_keff, off_npq, off_r2, off_tk, off_cnt,
         off_beg, off_cursor, off_uoff, off_xoff, off_xcnt, off_units, off_qent, off_slots, total;
     int nsweep, kcap, qw, lg;
     int64_t ucap;
@@ -181,6 +182,7 @@ SearchLayout layout_for(const ads_index *ix, int nq, int k_max, int nprobe_max, 
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + (bytes ? bytes : 1)); return at; };
     const size_t nqs = (size_t)(nq > 0 ? nq : 1);
     L.off_qrot = take(nqs * ix->D * sizeof(float));
+    L.off_qunit = take(ix->metric == ADS_METRIC_COSINE ? nqs * ix->D * sizeof(float) : 0);
     L.off_dots = take(nqs * ix->nlist * sizeof(float));
     L.off_probes = take(nqs * nprobe_max * sizeof(int32_t));
     L.off_kq = take(nqs * sizeof(int32_t));
@@ -320,7 +322,7 @@ extern "C" ads_status ads_rotate(const float *P, int32_t D, const float *X, int6
 
 extern "C" ads_status ads_ivf_build(const float *base, int64_t n, int32_t D, const float *P,
                                     const float *centroids, int32_t nlist, const int32_t *assign,
-                                    int32_t delta_d, int32_t storage, int32_t keep_fp32,
+                                    int32_t delta_d, int32_t storage, int32_t keep_fp32, int32_t metric,
                                     hipStream_t stream, ads_index **out) {
     if (!out) return fail(ADS_EINVAL, "out must not be NULL");
     *out = nullptr;
@@ -336,6 +338,7 @@ extern "C" ads_status ads_ivf_build(const float *base, int64_t n, int32_t D, con
     if (D % delta_d != 0) return fail(ADS_EINVAL, "delta_d=%d must divide D=%d", delta_d, D);
     if (storage != ADS_F32 && D % 8 != 0) return fail(ADS_EINVAL, "16-bit storage needs D %% 8 == 0");
     if (keep_fp32 != 0 && keep_fp32 != 1) return fail(ADS_EINVAL, "keep_fp32 must be 0 or 1");
+    if (metric != ADS_METRIC_L2 && metric != ADS_METRIC_COSINE) return fail(ADS_EINVAL, "unknown metric %d", metric);
     HIP_TRY(hipGetLastError(), "pending HIP error");
 
     std::vector<int32_t> h_assign;
@@ -381,7 +384,8 @@ extern "C" ads_status ads_ivf_build(const float *base, int64_t n, int32_t D, con
     ix->storage = storage;
     ix->keep_fp32 = keep_fp32;
     ix->max_list = max_list;
-    float *rot = nullptr;
+    ix->metric = metric;
+    float *rot = nullptr, *unit = nullptr;
     hipError_t e = hipSuccess;
 #define BUILD_TRY(expr, what)          \
     do {                               \
@@ -389,6 +393,7 @@ extern "C" ads_status ads_ivf_build(const float *base, int64_t n, int32_t D, con
         if (e != hipSuccess) {         \
             ads_status st = hip_fail(e, what); \
             if (rot) (void)hipFree(rot); \
+            if (unit) (void)hipFree(unit); \
             (void)hipStreamSynchronize(stream); \
             free_index(ix);            \
             if (e == hipErrorOutOfMemory) st = fail(ADS_ENOMEM, "%s: out of device memory", what); \
@@ -410,6 +415,11 @@ extern "C" ads_status ads_ivf_build(const float *base, int64_t n, int32_t D, con
     }
     if (keep_fp32) BUILD_TRY(dmalloc(&ix->rows32, (size_t)n * D, &ix->bytes), "alloc float32 rows");
     BUILD_TRY(hipMalloc(&rot, sizeof(float) * (size_t)n * D), "alloc rotation scratch");
+    if (metric == ADS_METRIC_COSINE) {
+        BUILD_TRY(dmalloc(&ix->norms, (size_t)n, &ix->bytes), "alloc norms");
+        const size_t rows = (size_t)(n > nlist ? n : nlist);
+        BUILD_TRY(hipMalloc(&unit, sizeof(float) * rows * D), "alloc normalisation scratch");
+    }
 
     BUILD_TRY(hipMemcpyAsync(ix->P, P, sizeof(float) * D * D, hipMemcpyDeviceToDevice, stream), "copy P");
     BUILD_TRY(hipMemcpyAsync(ix->list_off, off.data(), sizeof(int64_t) * (nlist + 1), hipMemcpyHostToDevice, stream), "upload offsets");
@@ -417,14 +427,27 @@ extern "C" ads_status ads_ivf_build(const float *base, int64_t n, int32_t D, con
     BUILD_TRY(hipMemcpyAsync(ix->pos_of, pos_of.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream), "upload positions");
     BUILD_TRY(hipMemcpyAsync(ix->list_of_pos, lop.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream), "upload list ids");
     // rotate every base vector (index phase, Section 6.1) and pack the lists
-    BUILD_TRY(gemm_nt_f32(base, D, ix->P, D, rot, D, n, D, D, stream), "rotate base");
+    const float *src = base;
+    if (metric == ADS_METRIC_COSINE) {
+        BUILD_TRY(launch_normalize(base, n, D, unit, ix->norms, stream), "normalise base");
+        src = unit;
+    }
+    BUILD_TRY(gemm_nt_f32(src, D, ix->P, D, rot, D, n, D, D, stream), "rotate base");
     BUILD_TRY(launch_pack(storage, rot, ix->ids, ix->list_of_pos, ix->list_off, n, D, delta_d, ix->data,
                           ix->rows32, stream), "pack lists");
-    BUILD_TRY(gemm_nt_f32(centroids, D, ix->P, D, ix->cent_rot, D, nlist, D, D, stream), "rotate centroids");
+    const float *csrc = centroids;
+    if (metric == ADS_METRIC_COSINE) {
+        BUILD_TRY(hipStreamSynchronize(stream), "synchronize");   // unit is reused below
+        BUILD_TRY(launch_normalize(centroids, nlist, D, unit, nullptr, stream), "normalise centroids");
+        csrc = unit;
+    }
+    BUILD_TRY(gemm_nt_f32(csrc, D, ix->P, D, ix->cent_rot, D, nlist, D, D, stream), "rotate centroids");
     BUILD_TRY(launch_row_norms(ix->cent_rot, nlist, D, ix->cent_norm, stream), "centroid norms");
     BUILD_TRY(hipStreamSynchronize(stream), "synchronize build");
     (void)hipFree(rot);
     rot = nullptr;
+    if (unit) (void)hipFree(unit);
+    unit = nullptr;
 #undef BUILD_TRY
     *out = ix;
     return ADS_OK;
@@ -439,6 +462,7 @@ extern "C" ads_status ads_index_info(const ads_index *ix, ads_index_desc *info) 
     info->storage = ix->storage;
     info->has_fp32_copy = ix->rows32 != nullptr;
     info->max_list = ix->max_list;
+    info->metric = ix->metric;
     info->device_bytes = ix->bytes;
     return ADS_OK;
 }
@@ -497,8 +521,37 @@ extern "C" ads_status ads_dco_batch(const ads_index *ix, const float *q_rot, con
     const float r2 = r * r;
     HIP_TRY(launch_dco(ix->storage, ix->data, ix->rows32, source, ix->list_off, ix->list_of_pos, ix->pos_of,
                        ix->n, ix->D, ix->dd, q_rot, cand, m, r2, (double)eps0, delta_d, method, pos_mask,
-                       dist, dims, reinterpret_cast<unsigned long long *>(stats), stream),
+                       dist, dims, reinterpret_cast<unsigned long long *>(stats), nullptr, stream),
             "dco_batch");
+    return ADS_OK;
+}
+
+extern "C" ads_status ads_dco_batch_ip(const ads_index *ix, const float *q, const int64_t *cand, int64_t m,
+                                       float r, float eps0, int32_t delta_d, int32_t method, uint8_t *pos_mask,
+                                       float *ip, int32_t *dims, int64_t *stats, hipStream_t stream) {
+    if (!ix) return fail(ADS_EINVAL, "index is NULL");
+    if (ix->metric != ADS_METRIC_COSINE) return fail(ADS_EINVAL, "inner-product DCOs need a cosine index");
+    if (m < 0) return fail(ADS_EINVAL, "m must be >= 0");
+    if (m == 0) return ADS_OK;
+    if (!q || !cand || !pos_mask || !ip) return fail(ADS_EINVAL, "q, cand, pos_mask and ip must not be NULL");
+    if (!std::isfinite(r)) return fail(ADS_EINVAL, "r must be finite");
+    if (!(eps0 >= 0.f)) return fail(ADS_EINVAL, "eps0 must be >= 0 (got %g)", (double)eps0);
+    if (delta_d < 1 || delta_d > ix->D) return fail(ADS_EINVAL, "delta_d must be in [1, D=%d] (got %d)", ix->D, delta_d);
+    if (method < 0 || method > 2) return fail(ADS_EINVAL, "unknown method %d", method);
+    HIP_TRY(hipGetLastError(), "pending HIP error");
+    const int D = ix->D;
+    float *scr = nullptr;
+    HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&scr), sizeof(float) * (2 * (size_t)D + 64), stream), "scratch");
+    float *qn = scr, *qr = scr + D, *qnorm = scr + 2 * D;
+    hipError_t e = launch_normalize(q, 1, D, qn, qnorm, stream);
+    if (e == hipSuccess) e = gemm_nt_f32(qn, D, ix->P, D, qr, D, 1, D, D, stream);
+    IpArgs ipa{ix->norms, qnorm, r};
+    if (e == hipSuccess)
+        e = launch_dco(ix->storage, ix->data, ix->rows32, 0, ix->list_off, ix->list_of_pos, ix->pos_of, ix->n, D,
+                       ix->dd, qr, cand, m, 0.f, (double)eps0, delta_d, method, pos_mask, ip, dims,
+                       reinterpret_cast<unsigned long long *>(stats), &ipa, stream);
+    (void)hipFreeAsync(scr, stream);
+    if (e != hipSuccess) return hip_fail(e, "dco_batch_ip");
     return ADS_OK;
 }
 
@@ -576,7 +629,13 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
     // 1. query rotation (Section 3.1) and centre inner products (MFMA)
     {
         PhaseTimer t(ADS_PHASE_ROTATE, stream);
-        SEARCH_TRY(gemm_nt_f32(q, D, ix->P, D, qrot, D, nq, D, D, stream), "rotate queries");
+        const float *qsrc = q;
+        if (ix->metric == ADS_METRIC_COSINE) {
+            float *qunit = reinterpret_cast<float *>(ws + L.off_qunit);
+            SEARCH_TRY(launch_normalize(q, nq, D, qunit, nullptr, stream), "normalise queries");
+            qsrc = qunit;
+        }
+        SEARCH_TRY(gemm_nt_f32(qsrc, D, ix->P, D, qrot, D, nq, D, D, stream), "rotate queries");
     }
     // 2. probe selection
     {

@@ -14,15 +14,33 @@ __global__ __launch_bounds__(ADS_WG) void dco_kernel(
     const int32_t *__restrict__ pos_of, int64_t n, int D, int dd, const float *__restrict__ q,
     const int64_t *__restrict__ cand, int64_t m, float r2, double eps0, int step, int method,
     uint8_t *__restrict__ mask, float *__restrict__ dist, int32_t *__restrict__ dims,
-    unsigned long long *stats) {
+    unsigned long long *stats, IpArgs ipa) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long c_dco = 0, c_dims = 0, c_pos = 0;
+    const bool ip = ipa.onorm != nullptr;
+    float nn = 0.f;
+    if (i < m && ip) {
+        const int64_t id = cand[i];
+        if (id >= 0 && id < n) {
+            // <o,q> >= r  <=>  |o/|o| - q/|q||^2 <= 2 - 2 r / (|o||q|)   (Section 7)
+            nn = ipa.onorm[id] * (*ipa.qnorm);
+            r2 = nn > 0.f ? 2.f - 2.f * ipa.r_ip / nn : (ipa.r_ip <= 0.f ? __builtin_inff() : -1.f);
+        }
+    }
     if (i < m) {
         const int64_t id = cand[i];
         if (id < 0 || id >= n) {
             mask[i] = 0;
             dist[i] = __builtin_nanf("");
             if (dims) dims[i] = -1;
+        } else if (ip && (r2 < 0.f || nn == 0.f)) {
+            // unreachable threshold, or a zero vector: decided without sampling
+            const bool positive = nn == 0.f && ipa.r_ip <= 0.f;
+            mask[i] = positive ? 1 : 0;
+            dist[i] = positive ? 0.f : -__builtin_inff();
+            if (dims) dims[i] = 0;
+            c_dco = 1;
+            c_pos = positive;
         } else {
             const int64_t p = pos_of[id];
             const int l = list_of_pos[p];
@@ -62,7 +80,8 @@ __global__ __launch_bounds__(ADS_WG) void dco_kernel(
             }
             const bool positive = !done && s <= r2;
             mask[i] = positive ? 1 : 0;
-            dist[i] = positive ? __fsqrt_rn(s) : __builtin_inff();
+            if (ip) dist[i] = positive ? nn * (1.f - 0.5f * s) : -__builtin_inff();
+            else dist[i] = positive ? __fsqrt_rn(s) : __builtin_inff();
             if (dims) dims[i] = used;
             c_dco = 1;
             c_dims = (unsigned long long)used;
@@ -126,6 +145,23 @@ __global__ __launch_bounds__(ADS_WG) void pack_kernel(
     }
 }
 
+// out[r] = x[r] / |x[r]| (a zero row stays zero), norms[r] = |x[r]|.
+__global__ __launch_bounds__(ADS_WG) void normalize_kernel(const float *x, int64_t n, int D, float *out,
+                                                          float *norms) {
+    const int64_t r = blockIdx.x;
+    if (r >= n) return;
+    float acc = 0.f;
+    for (int i = threadIdx.x; i < D; i += ADS_WG) acc = __fmaf_rn(x[r * D + i], x[r * D + i], acc);
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o);
+    __shared__ float red[ADS_WG / 64];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    const float nrm = __fsqrt_rn(red[0] + red[1] + red[2] + red[3]);
+    const float inv = nrm > 0.f ? 1.f / nrm : 0.f;
+    for (int i = threadIdx.x; i < D; i += ADS_WG) out[r * D + i] = x[r * D + i] * inv;
+    if (threadIdx.x == 0 && norms) norms[r] = nrm;
+}
+
 __global__ __launch_bounds__(ADS_WG) void row_norms_kernel(const float *x, int64_t n, int D, float *out) {
     const int64_t r = blockIdx.x;
     if (r >= n) return;
@@ -144,24 +180,26 @@ hipError_t launch_dco(int dtype, const void *data, const float *rows32, int sour
                       const int64_t *list_off, const int32_t *list_of_pos, const int32_t *pos_of,
                       int64_t n, int D, int dd_layout, const float *q, const int64_t *cand,
                       int64_t m, float r2, double eps0, int step, int method, uint8_t *mask,
-                      float *dist, int32_t *dims, unsigned long long *stats, hipStream_t s) {
+                      float *dist, int32_t *dims, unsigned long long *stats, const IpArgs *ip,
+                      hipStream_t s) {
     if (m <= 0) return hipSuccess;
     const unsigned grid = (unsigned)((m + ADS_WG - 1) / ADS_WG);
+    const IpArgs ipa = ip ? *ip : IpArgs{nullptr, nullptr, 0.f};
     switch (dtype) {
         case ADS_F32:
             hipLaunchKernelGGL(dco_kernel<ADS_F32>, dim3(grid), dim3(ADS_WG), 0, s, data, rows32, source,
                                list_off, list_of_pos, pos_of, n, D, dd_layout, q, cand, m, r2, eps0,
-                               step, method, mask, dist, dims, stats);
+                               step, method, mask, dist, dims, stats, ipa);
             break;
         case ADS_BF16:
             hipLaunchKernelGGL(dco_kernel<ADS_BF16>, dim3(grid), dim3(ADS_WG), 0, s, data, rows32, source,
                                list_off, list_of_pos, pos_of, n, D, dd_layout, q, cand, m, r2, eps0,
-                               step, method, mask, dist, dims, stats);
+                               step, method, mask, dist, dims, stats, ipa);
             break;
         case ADS_F16:
             hipLaunchKernelGGL(dco_kernel<ADS_F16>, dim3(grid), dim3(ADS_WG), 0, s, data, rows32, source,
                                list_off, list_of_pos, pos_of, n, D, dd_layout, q, cand, m, r2, eps0,
-                               step, method, mask, dist, dims, stats);
+                               step, method, mask, dist, dims, stats, ipa);
             break;
         default:
             return hipErrorInvalidValue;
@@ -191,6 +229,12 @@ hipError_t launch_pack(int dtype, const float *rot, const int32_t *ids, const in
         default:
             return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_normalize(const float *x, int64_t n, int D, float *out, float *norms, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(normalize_kernel, dim3((unsigned)n), dim3(ADS_WG), 0, s, x, n, D, out, norms);
     return hipGetLastError();
 }
 

@@ -31,11 +31,21 @@ hipError_t launch_scan(const ScanArgs &a, int dtype, int dd, int qw, int grid, h
 int num_sweeps(int nprobe_max, int lg);
 int sweep_begin(int s, int lg);
 
+// Inner-product mode of the explicit-candidate DCO (all NULL / 0 for L2).
+struct IpArgs {
+    const float *onorm;     // [n] raw norm of each base vector, by id
+    const float *qnorm;     // device scalar: raw norm of the query
+    float r_ip;             // inner-product threshold
+};
+
 hipError_t launch_dco(int dtype, const void *data, const float *rows32, int source,
                       const int64_t *list_off, const int32_t *list_of_pos, const int32_t *pos_of,
                       int64_t n, int D, int dd_layout, const float *q, const int64_t *cand,
                       int64_t m, float r2, double eps0, int step, int method, uint8_t *mask,
-                      float *dist, int32_t *dims, unsigned long long *stats, hipStream_t s);
+                      float *dist, int32_t *dims, unsigned long long *stats, const IpArgs *ip,
+                      hipStream_t s);
+
+hipError_t launch_normalize(const float *x, int64_t n, int D, float *out, float *norms, hipStream_t s);
 
 hipError_t launch_pack(int dtype, const float *rot, const int32_t *ids, const int32_t *list_of_pos,
                        const int64_t *list_off, int64_t n, int D, int dd, void *data,

@@ -262,3 +262,56 @@ def test_search_distances_equal_dco_batch(ads, ivf960):
             v = ids[i] >= 0
             m, d, _ = ads.dco_batch(ix, qr[i], ids[i][v], math.inf, math.inf, 32)
             assert np.array_equal(_np(d), dist[i][v])
+
+
+# ---------------------------------------------------------------------------
+# Section 7: cosine search and inner-product comparisons
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def cosine(ads):
+    w = Workload("lowrank", 20_000, 30, 256, 32, 4002, latent=16, noise=0.2)
+    P32, _ = ads.make_rotation(w.G)
+    xu = oracle.normalize(w.x).astype(np.float32)
+    cu = oracle.normalize(w.cent).astype(np.float32)
+    ix = ads.ivf_build(w.x, P32, w.cent, w.assign, delta_d=32, storage=ads.F32, keep_fp32=True,
+                       metric=ads.METRIC_COSINE)
+    return w, ix, xu, cu
+
+
+def test_cosine_search_matches_oracle_on_unit_vectors(ads, cosine):
+    w, ix, xu, cu = cosine
+    ids, dist, probes = ads.search(ix, w.q, 10, 6, eps0=math.inf, want_probes=True)
+    ids, dist, probes = _np(ids), _np(dist), _np(probes)
+    qu = oracle.normalize(w.q)
+    xr, qr, cr = oracle.rotate(xu, w.P64), oracle.rotate(qu, w.P64), oracle.rotate(cu, w.P64)
+    pr, _ = oracle.probes(qr, cr, 6)
+    o_ids, o_d, _ = oracle.ivf_search(xr, qr, w.off, w.members, pr, 10, math.inf, 32,
+                                      method=oracle.METHOD_FDS)
+    same = 0
+    for i in range(w.nq):
+        if list(probes[i]) == list(pr[i]):
+            same += 1
+            assert tie_band_equal(ids[i], dist[i], o_ids[i], o_d[i]), i
+    assert same >= w.nq - 2
+    # cosine similarity of the results, 1 - d^2 / 2, equals the direct cosine
+    cosv = np.array([[float(xu[j] @ qu[i]) for j in row] for i, row in enumerate(ids)])
+    assert np.allclose(1 - dist.astype(np.float64) ** 2 / 2, cosv, atol=2e-6)
+
+
+@pytest.mark.parametrize("eps0,step", [(math.inf, 32), (2.1, 32), (1.0, 8)])
+def test_inner_product_dco_matches_oracle(ads, cosine, eps0, step):
+    w, ix, xu, cu = cosine
+    cand = np.arange(0, w.n, 3, dtype=np.int64)
+    for qi in (0, 9):
+        ipd = w.x[cand].astype(np.float64) @ w.q[qi].astype(np.float64)
+        r = float(np.quantile(ipd, 0.97))
+        mask, ip, dims = ads.dco_batch_ip(ix, w.q[qi], cand, r, eps0, step)
+        mask, ip, dims = _np(mask), _np(ip), _np(dims)
+        ref = oracle.ip_dco_batch(w.x, w.q[qi], cand, r, w.P64, eps0, step)
+        diff = mask != ref["mask"]
+        assert np.all(ref["band"][diff] == 1), "mask mismatch outside the band"
+        pos = (mask == 1) & (ref["mask"] == 1)
+        scale = np.linalg.norm(w.x[cand[pos]], axis=1) * np.linalg.norm(w.q[qi])
+        assert np.all(np.abs(ip[pos] - ref["ip"][pos]) <= 1e-5 * scale)
+        assert np.all(np.isinf(ip[mask == 0]))

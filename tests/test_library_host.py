@@ -65,7 +65,7 @@ def test_calls_validate_before_launching(ads):
     assert "index is NULL" in ads.last_error()
     assert lib.ads_dco_batch(None, None, None, 1, 1.0, 2.1, 32, 0, 0, None, None, None, None, None) == -1
     out = ctypes.c_void_p()
-    assert lib.ads_ivf_build(None, 10, 128, None, None, 4, None, 32, 0, 1, None, ctypes.byref(out)) == -1
+    assert lib.ads_ivf_build(None, 10, 128, None, None, 4, None, 32, 0, 1, 0, None, ctypes.byref(out)) == -1
     assert "must not be NULL" in ads.last_error()
     assert lib.ads_rotate(None, 128, None, 0, None, None) == 0   # n == 0 is a no-op
     assert lib.ads_rotate(None, 128, None, 5, None, None) == -1

@@ -387,3 +387,42 @@ def test_recall_and_ratio_metrics_hand_cases():
     d2 = np.array([[1.0, np.inf, np.inf]])
     assert oracle.recall(ids2, d2, gt, 3) == pytest.approx(1 / 3)
     assert oracle.dims_ratio(np.array([[10, 320, 1]]), 128) == pytest.approx(0.25)
+
+
+# --------------------------------------------------------------------------
+# Section 7: cosine similarity and inner product
+# --------------------------------------------------------------------------
+
+def test_inner_product_reduction_matches_direct_comparison():
+    """With eps0 = +inf the reduced DCO decides <o,q> >= r exactly (away from
+    rounding at the boundary) and returns <o,q>."""
+    rng = np.random.default_rng(21)
+    D = 48
+    x = rng.standard_normal((400, D)) * rng.uniform(0.5, 3.0, size=(400, 1))
+    x[7] = 0.0                                     # a zero vector
+    q = rng.standard_normal(D)
+    P = oracle.make_rotation(sd.gaussian_matrix(D, 22))
+    ipd = x @ q
+    for r in (np.quantile(ipd, 0.9), 0.0, -2.0, np.max(np.linalg.norm(x, axis=1)) * np.linalg.norm(q) * 1.01):
+        res = oracle.ip_dco_batch(x, q, np.arange(400), r, P, math.inf, 8)
+        clear = np.abs(ipd - r) > 1e-9 * (1 + abs(r))
+        assert np.array_equal(res["mask"][clear] == 1, ipd[clear] >= r)
+        pos = res["mask"] == 1
+        assert np.allclose(res["ip"][pos], ipd[pos], rtol=1e-12, atol=1e-10)
+    # unreachable threshold: r above |o||q| can never be met, decided with 0 dims
+    res = oracle.ip_dco_batch(x, q, np.arange(400), 1e9, P, 2.1, 8)
+    assert res["mask"].sum() == 0 and np.all(res["dims"] == 0)
+
+
+def test_cosine_search_is_euclidean_search_on_unit_vectors():
+    """Cosine search (largest cosine first) equals the Euclidean KNN of the
+    normalised vectors (Section 7)."""
+    x = sd.lowrank(3000, 32, 61, 62, latent=8, noise=0.3)
+    q = sd.lowrank(5, 32, 63, 62, latent=8, noise=0.3)
+    xu, qu = oracle.normalize(x), oracle.normalize(q)
+    ids, dist = oracle.brute_knn(xu.astype(np.float32), qu, 5)
+    cos = (xu @ qu.T).T
+    for i in range(5):
+        top = np.argsort(-cos[i], kind="stable")[:5]
+        assert set(top.tolist()) == set(ids[i].tolist())
+        assert np.allclose(1 - dist[i] ** 2 / 2, cos[i][ids[i]], atol=1e-6)
