@@ -67,6 +67,9 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device-to-device copy first (reference kernel "
                          "of known size for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
+    ap.add_argument("--dense-mfma", type=int, default=0, choices=[0, 1],
+                    help="ADSampling scan variant: 1 = dense phase on the matrix cores, "
+                         "0 = register-dense phase (default; same results)")
     ap.add_argument("--nprobe", type=int, default=None,
                     help="use this nprobe for both methods instead of searching for the "
                          "smallest one that reaches the target recall")
@@ -99,6 +102,7 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     ads.load()
+    ads.set_tuning(dense_mfma=args.dense_mfma)
     w = sd.WORKLOADS[args.workload]
     if args.nq or args.n:
         w = w.scaled(nq=args.nq or w.nq, n=args.n or w.n)

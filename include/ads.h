@@ -143,6 +143,9 @@ ads_status ads_rotate(const float *P, int32_t D, const float *X, int64_t n, floa
  * (all vectors' first block contiguous, then the second block, ...): the
  * cache-friendly arrangement of Section 5.2 generalised from two arrays to
  * one array per block.  Within a list, vectors keep ascending id order.
+ * The index also holds the float32 squared norm of every stored block and of
+ * every stored vector (4 (D/delta_d + 1) bytes per vector), which the
+ * matrix-core scan uses for its dot-product form and rounding margins.
  * Synchronises the stream once (the list sizes are needed on the host).
  * Errors: ADS_EINVAL (sizes, ids out of range), ADS_ENOMEM, ADS_EHIP.
  */
@@ -255,7 +258,8 @@ ads_status ads_search(const ads_index *ix, const float *q, int32_t nq, const int
                       int32_t *probes_out, int64_t *stats, void *workspace, hipStream_t stream);
 
 /* ads_search_workspace_size -- HOST: bytes of workspace ads_search needs for
- * these sizes (0 on invalid arguments, with ads_last_error set). */
+ * these sizes under the calling thread's queries_per_unit setting, for any
+ * method, eps0 and dense_mfma (0 on invalid arguments, with ads_last_error set). */
 uint64_t ads_search_workspace_size(const ads_index *ix, int32_t nq, int32_t k_max,
                                    int32_t nprobe_max, int32_t rerank);
 
@@ -297,12 +301,19 @@ typedef struct {
     float dense_frac;         /* (0, 0.25]: a 64-vector slice leaves the register-dense
                                  phase once at most this fraction of its (vector, query)
                                  pairs is alive.  Default 0.125. */
-    int32_t queries_per_unit; /* 1, 2, 4, 8 or 16 queries per work unit; 0 = the largest of
-                                 1..8 whose KNN sets fit in 4 KB of LDS.  Default 0. */
+    int32_t queries_per_unit; /* 1, 2, 4, 8 or 16 queries per work unit; 0 = the largest
+                                 power of two up to 8 (16 with dense_mfma) whose KNN sets fit
+                                 in 4 KB of LDS.  Default 0. */
     int32_t sweep_log2;       /* probe ranks are scanned in sweeps [0,1), [1,g), [g,g^2), ...
                                  with g = 2^sweep_log2, sweep_log2 in [1, 6].  Default 3. */
     int32_t grid_per_xcd;     /* persistent scan workgroups per XCD, 0 = as many as the
                                  sweep has units (capped at 4096).  Default 0. */
+    int32_t dense_mfma;       /* 1: ADSampling / PDScanning scans evaluate the dense phase in
+                                 the dot-product form on the matrix cores and re-run, in the
+                                 canonical form, every pair whose decision the rounding
+                                 bound cannot settle (same results as 0); 0: register-dense
+                                 phase in the canonical form.  FDScanning always uses 0.
+                                 Default 0. */
 } ads_tuning;
 
 /* ads_set_tuning / ads_get_tuning -- HOST, per thread: knobs for later

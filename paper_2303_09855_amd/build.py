@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libads.so")
-SOURCES = ["api.hip", "scan.hip", "gemm.hip", "dco.hip"]
+SOURCES = ["api.hip", "scan.hip", "scan_mfma.hip", "gemm.hip", "dco.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

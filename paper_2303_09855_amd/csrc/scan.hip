@@ -16,20 +16,20 @@
 // rebuilds the KNN set.  A query's result depends only on that query, never
 // on the rest of the batch.
 //
-// Execution.  A unit runs on a workgroup of four waves.  Units are laid out
-// XCD-major: workgroup w serves the units of XCD (w mod 8), so every unit of
-// a list lands on the same XCD and shares that XCD's L2.  The list is cut into
-// 64-vector slices, one slice per wave per round; the waves of a round run
-// independently (wave-private LDS, no workgroup barrier) and the round's
-// positives are folded into the unit's local KNN sets afterwards.  In a slice
-// a lane owns one vector: while at least half of the slice's (vector, query)
-// pairs are alive, the lane keeps the vector's DD coordinates of the current
-// block in registers and walks the unit's queries (query coordinates
-// broadcast from LDS).  Then the surviving pairs are compacted into an LDS
-// list and each lane runs its pairs to the end independently (a per-lane state
-// machine over the remaining blocks: no barrier per block, long chains overlap
-// short ones).
-#include "kernels.h"
+// Execution.  A unit runs on one wave.  Units are laid out XCD-major:
+// workgroup w serves the units of XCD (w mod 8), so every unit of a list lands
+// on the same XCD and shares that XCD's L2.  The list is cut into 64-vector
+// tiles.  In a tile a lane owns one vector: while more than dense_frac of the
+// tile's (vector, query) pairs are alive, the lane keeps the vector's DD
+// coordinates of the current block in registers and walks the unit's queries
+// (query coordinates broadcast from LDS).  Then the surviving pairs are
+// compacted into an LDS list and finish in the pair-list phase
+// (scan_sparse.h).  The tile's positives are folded into each query's local
+// KNN set and lower its threshold before the next tile.
+//
+// This is the register-dense variant; scan_mfma.hip evaluates the dense phase
+// on the matrix cores and takes the same decisions.
+#include "scan_sparse.h"
 
 namespace ads {
 
@@ -49,32 +49,8 @@ struct ScanSmem {
     // followed by float coef[nb] and uint64 tk[QW][kcap]
 };
 
-// Orders this wave's LDS accesses (lanes of one wave run in lockstep).
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
-template <int DT, int DD>
-__device__ __forceinline__ float block_partial(const unsigned char *op, const float *qp, float s) {
-#pragma unroll
-    for (int k0 = 0; k0 < DD; k0 += 8) {
-        float o[8];
-        load_elems<DT, 8>(op + k0 * Elem<DT>::bytes, o);
-        const float4 q0 = *reinterpret_cast<const float4 *>(qp + k0);
-        const float4 q1 = *reinterpret_cast<const float4 *>(qp + k0 + 4);
-        const float qv[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            float df = o[k] - qv[k];
-            s = __fmaf_rn(df, df, s);
-        }
-    }
-    return s;
-}
-
 template <int DT, int DD, int QW>
-__global__ __launch_bounds__(64 * SCAN_WAVES) void scan_kernel(ScanArgs a) {
+__global__ __launch_bounds__(64 * SCAN_WAVES) __attribute__((amdgpu_waves_per_eu(4))) void scan_kernel(ScanArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     ScanSmem<DD, QW> &sm = *reinterpret_cast<ScanSmem<DD, QW> *>(smem_raw);
     float *coef = reinterpret_cast<float *>(smem_raw + sizeof(ScanSmem<DD, QW>));
@@ -212,82 +188,30 @@ __global__ __launch_bounds__(64 * SCAN_WAVES) void scan_kernel(ScanArgs a) {
                     break;
                 }
             }
-            // sparse phase: all surviving pairs sit at the same next block
-            // bcur.  With n pairs left, each pair takes G = 64 / n lanes (a
-            // power of two) that evaluate blocks bcur .. bcur+G-1 at once; an
-            // in-group scan gives S at every block boundary and the first
-            // rejecting block is found with a ballot, so the decisions are
-            // those of testing block by block.  Survivors advance by G blocks
-            // together and are compacted into the other list.  S is always
-            // the sum of per-block partials in block order, so a pair's result
-            // does not depend on G or on when it left the dense phase.
+            // the surviving pairs run to their decisions in the pair-list phase
             if (sparse) {
-                int bcur = b, cur = 0, n = m;
-                while (n > 0 && bcur < nb) {
-                    wave_sync();
-                    int G = 1;
-                    while (G * 2 * n <= 64 && G * 2 <= nb - bcur) G *= 2;
-                    const int ppr = 64 / G;                 // pairs per round
-                    const int gi = lane & (G - 1);
-                    const uint64_t *src = sm.list[w][cur];
-                    uint64_t *dst = sm.list[w][cur ^ 1];
-                    int nout = 0;
-                    for (int r0p = 0; r0p < n; r0p += ppr) {
-                        const int pi = r0p + lane / G;
-                        const bool pv = pi < n;
-                        const uint64_t en = pv ? src[pi] : 0ull;
-                        const float s0 = __uint_as_float((uint32_t)(en >> 32));
-                        const int jj = (int)(((uint32_t)en >> 6) & 31u), vv = (int)(en & 63u);
-                        const int blk = bcur + gi;
-                        const bool bv = pv && blk < nb;
-                        float part = 0.f;
-                        if (bv) {
-                            const unsigned char *op = lbase + ((int64_t)blk * nl * DD + (int64_t)(vc + vv) * DD) * EB;
-                            part = block_partial<DT, DD>(op, a.qrot + (int64_t)sm.qidx[jj] * D + blk * DD, 0.f);
-                        }
-                        // S after each block, added in block order (the canonical
-                        // order, independent of G): one lane of the group per round
-                        float sb = gi == 0 ? s0 + part : 0.f;
-                        for (int t = 1; t < G; ++t) {
-                            const float prev = __shfl_up(sb, 1, G);
-                            if (gi == t) sb = prev + part;
-                        }
-                        const int d = (blk + 1) * DD;
-                        const float r2 = pv ? sm.r2s[jj] : 0.f;
-                        const bool rej = bv && d < D && test_reject(sb, coef[bv ? blk : 0], r2);
-                        const uint64_t rm = __ballot(rej);
-                        const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (lane & ~(G - 1)));
-                        const uint64_t grm = rm & gmask;
-                        // the group's last block and the value of S there
-                        const int glast = min(G, nb - bcur) - 1;
-                        const float slast = __shfl(sb, (lane & ~(G - 1)) + glast, 64);
-                        bool keep = false;
-                        if (pv && gi == 0) {
-                            if (grm) {
-                                const int first = __ffsll((long long)grm) - 1 - (lane & ~(G - 1));
-                                my_dims += (unsigned long long)(bcur + first + 1) * DD;
-                            } else if (bcur + glast + 1 >= nb) {
-                                my_dims += D;
-                                if (slast <= r2) {
-                                    const int p = atomicAdd(&pcnt[jj], 1);
-                                    sm.pos[w][jj][p] = make_key(slast, (uint32_t)a.ids[off + vc + vv]);
-                                    ++my_pos;
-                                }
-                            } else {
-                                keep = true;
-                            }
-                        }
-                        const uint64_t km = __ballot(keep);
-                        if (keep) {
-                            const int p = nout + __popcll(km & lanemask_lt);
-                            dst[p] = ((uint64_t)__float_as_uint(slast) << 32) | (uint32_t)(en & 0xffffffffu);
-                        }
-                        nout += __popcll(km);
-                    }
-                    n = nout;
-                    cur ^= 1;
-                    bcur += G;
-                }
+                SparseCtx ctx;
+                ctx.lbase = lbase;
+                ctx.nl = nl;
+                ctx.vc = vc;
+                ctx.qrot = a.qrot;
+                ctx.qidx = sm.qidx;
+                ctx.r2s = sm.r2s;
+                ctx.coef = coef;
+                ctx.D = D;
+                ctx.nb = nb;
+                ctx.vmarg = nullptr;
+                ctx.qmarg = nullptr;
+                ctx.exq = nullptr;
+                const int32_t *tids = a.ids + off + vc;
+                uint64_t(*pos)[64] = sm.pos[w];
+                auto sink = [=](int jj, float s, int vv) {
+                    const int p = atomicAdd(&pcnt[jj], 1);
+                    pos[jj][p] = make_key(s, (uint32_t)tids[vv]);
+                };
+                const SparseOut so = sparse_run<DT, DD, false>(ctx, sm.list[w][0], sm.list[w][1], m, b, 0, sink);
+                my_dims += so.dims;
+                my_pos += so.pos;
             }
             __syncthreads();
             // fold the round's positives into each query's local KNN set

@@ -264,6 +264,47 @@ def test_search_distances_equal_dco_batch(ads, ivf960):
             assert np.array_equal(_np(d), dist[i][v])
 
 
+_MC_CASES = [
+    # fixture, delta_d, storage, method, eps0, K, nprobe, queries_per_unit
+    ("ivf960", 32, 0, 0, 2.1, 10, 8, 0),
+    ("ivf960", 16, 0, 0, 1.0, 10, 8, 4),
+    ("ivf960", 64, 1, 0, 2.1, 40, 8, 0),
+    ("ivf960", 8, 2, 0, 2.1, 10, 6, 1),
+    ("ivf128", 32, 0, 0, 2.1, 10, 16, 16),
+    ("ivf128", 16, 0, 2, 2.1, 10, 16, 0),
+    ("ivf128", 8, 0, 0, 0.5, 100, 8, 0),
+    ("ivf128", 32, 1, 0, 2.1, 10, 64, 8),
+]
+
+
+@pytest.mark.parametrize("fixture,dd,storage,method,eps0,K,nprobe,qpu", _MC_CASES)
+def test_matrix_core_scan_equals_register_scan(ads, request, fixture, dd, storage, method, eps0, K,
+                                               nprobe, qpu):
+    """The matrix-core dense phase (dot-product form) acts only on decisions
+    its rounding bound settles and sends every other pair through the
+    canonical form, so ids, distances and every statistic (DCOs, sampled
+    dimensions, positives) equal those of the register-dense scan bit for bit.
+    The mixture data of ivf128 sits far from the origin (norms ~20x the
+    distances), which puts many tests inside the rounding band."""
+    w, _ = request.getfixturevalue(fixture)
+    ix = _build(ads, w, dd=dd, storage=storage)
+    saved = ads.get_tuning()
+    res = {}
+    try:
+        for mf in (0, 1):
+            ads.set_tuning(dense_mfma=mf, queries_per_unit=qpu)
+            stats = torch.zeros(ads.NSTATS, dtype=torch.int64, device="cuda")
+            ids, dist = ads.search(ix, w.q, K, nprobe, eps0=eps0, method=method, stats=stats)
+            res[mf] = (_np(ids), _np(dist), _np(stats))
+    finally:
+        ads.set_tuning(**saved)
+        ix.free()
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][1], res[1][1])
+    assert np.array_equal(res[0][2], res[1][2]), (res[0][2], res[1][2])
+    assert res[1][2][ads.STAT_DIMS] < res[1][2][ads.STAT_DCOS] * w.D
+
+
 # ---------------------------------------------------------------------------
 # Section 7: cosine search and inner-product comparisons
 # ---------------------------------------------------------------------------
