@@ -163,6 +163,11 @@ int qw_for(int kcap, bool mfma) {
 }
 
 constexpr int KCAP_MAX = 512;
+// Sweeps with fewer work units than this run the prefetching register scan.
+#ifndef ADS_PREFETCH_UNITS
+#define ADS_PREFETCH_UNITS 8192
+#endif
+constexpr int64_t PREFETCH_UNITS = ADS_PREFETCH_UNITS;
 constexpr int NPROBE_MAX_LIMIT = 8192;
 
 struct SearchLayout {
@@ -721,7 +726,7 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
             if (L.mfma)
                 SEARCH_TRY(launch_scan_mfma(a, ix->storage, ix->dd, qw, (int)(8 * P), stream), "scan");
             else
-                SEARCH_TRY(launch_scan(a, ix->storage, ix->dd, qw, (int)(8 * P), stream), "scan");
+                SEARCH_TRY(launch_scan(a, ix->storage, ix->dd, qw, (int)(8 * P), units_bound < PREFETCH_UNITS, stream), "scan");
         }
         const size_t sh = sizeof(uint64_t) * (size_t)next_pow2(L.kcap);
         PhaseTimer tm(ADS_PHASE_MERGE, stream);

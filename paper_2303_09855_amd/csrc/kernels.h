@@ -31,7 +31,7 @@ struct ScanArgs {
     float kappa;            // margin factor of the dot-product form
 };
 
-hipError_t launch_scan(const ScanArgs &a, int dtype, int dd, int qw, int grid, hipStream_t s);
+hipError_t launch_scan(const ScanArgs &a, int dtype, int dd, int qw, int grid, bool prefetch, hipStream_t s);
 hipError_t launch_scan_mfma(const ScanArgs &a, int dtype, int dd, int qw, int grid, hipStream_t s);
 float scan_margin_kappa(int dd, int nb);
 

@@ -39,7 +39,7 @@ template <int DD, int QW>
 struct ScanSmem {
     static constexpr int LCAP = 16 * QW;   // pairs alive when the dense phase hands over (<= 1/4)
     // wave-private
-    float qs[SCAN_WAVES][QW][DD + 4];
+    float qs[SCAN_WAVES][2][QW][DD + 4];     // query block, double-buffered
     uint64_t list[SCAN_WAVES][2][LCAP];
     uint64_t pos[SCAN_WAVES][QW][64];
     int pcnt[SCAN_WAVES][QW];
@@ -49,8 +49,10 @@ struct ScanSmem {
     // followed by float coef[nb] and uint64 tk[QW][kcap]
 };
 
-template <int DT, int DD, int QW>
-__global__ __launch_bounds__(64 * SCAN_WAVES) __attribute__((amdgpu_waves_per_eu(4))) void scan_kernel(ScanArgs a) {
+// PF: fetch the next block of the dense phase while the current one is
+// evaluated (more registers; for sweeps with fewer units than wave slots).
+template <int DT, int DD, int QW, bool PF>
+__global__ __launch_bounds__(64 * SCAN_WAVES) __attribute__((amdgpu_waves_per_eu(PF ? 2 : 4))) void scan_kernel(ScanArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     ScanSmem<DD, QW> &sm = *reinterpret_cast<ScanSmem<DD, QW> *>(smem_raw);
     float *coef = reinterpret_cast<float *>(smem_raw + sizeof(ScanSmem<DD, QW>));
@@ -65,7 +67,6 @@ __global__ __launch_bounds__(64 * SCAN_WAVES) __attribute__((amdgpu_waves_per_eu
     const int D = a.D, nb = a.nb, kcap = a.kcap;
     constexpr int EB = Elem<DT>::bytes;
     const uint64_t lanemask_lt = (1ull << lane) - 1ull;
-    float(*qs)[DD + 4] = sm.qs[w];
     int *pcnt = sm.pcnt[w];
 
     for (int b = tid; b < nb; b += 64 * SCAN_WAVES) {
@@ -120,17 +121,48 @@ __global__ __launch_bounds__(64 * SCAN_WAVES) __attribute__((amdgpu_waves_per_eu
             bool sparse = false;
             wave_sync();
             // dense phase: lane = vector, the unit's queries in turn
-            for (; tile_pairs > 0 && b < nb; ++b) {
-                float o[DD];
-                if (alive) load_elems<DT, DD>(lbase + ((int64_t)b * nl * DD + (int64_t)v * DD) * EB, o);
-                for (int i = lane; i < QW * (DD / 4); i += 64) {
+            constexpr int QPL = (QW * (DD / 4) + 63) / 64;    // query float4 per lane per block
+            auto fetch_q = [&](int bb, float4 *qv) {
+#pragma unroll
+                for (int u = 0; u < QPL; ++u) {
+                    const int i = lane + 64 * u;
                     const int jj = i / (DD / 4), k4 = (i % (DD / 4)) * 4;
-                    if (jj < qc) {
-                        const float4 t = *reinterpret_cast<const float4 *>(a.qrot + (int64_t)sm.qidx[jj] * D + b * DD + k4);
-                        qs[jj][k4 + 0] = t.x; qs[jj][k4 + 1] = t.y;
-                        qs[jj][k4 + 2] = t.z; qs[jj][k4 + 3] = t.w;
+                    if (i < QW * (DD / 4) && jj < qc)
+                        qv[u] = *reinterpret_cast<const float4 *>(a.qrot + (int64_t)sm.qidx[jj] * D + bb * DD + k4);
+                }
+            };
+            auto store_q = [&](const float4 *qv, float (*qd)[DD + 4]) {
+#pragma unroll
+                for (int u = 0; u < QPL; ++u) {
+                    const int i = lane + 64 * u;
+                    const int jj = i / (DD / 4), k4 = (i % (DD / 4)) * 4;
+                    if (i < QW * (DD / 4) && jj < qc) {
+                        qd[jj][k4 + 0] = qv[u].x; qd[jj][k4 + 1] = qv[u].y;
+                        qd[jj][k4 + 2] = qv[u].z; qd[jj][k4 + 3] = qv[u].w;
                     }
                 }
+            };
+            float o[DD];
+            int qb = 0;                       // qs buffer of the current block
+            if (PF && tile_pairs > 0) {
+                float4 qv[QPL];
+                fetch_q(0, qv);
+                if (alive) load_elems<DT, DD>(lbase + ((int64_t)v * DD) * EB, o);
+                store_q(qv, sm.qs[w][0]);
+            }
+            for (; tile_pairs > 0 && b < nb; ++b) {
+                float o1[DD];
+                float4 qv1[QPL];
+                if constexpr (PF) {
+                    const int bn = b + 1 < nb ? b + 1 : b;
+                    fetch_q(bn, qv1);
+                    if (alive) load_elems<DT, DD>(lbase + ((int64_t)bn * nl * DD + (int64_t)v * DD) * EB, o1);
+                } else {
+                    if (alive) load_elems<DT, DD>(lbase + ((int64_t)b * nl * DD + (int64_t)v * DD) * EB, o);
+                    fetch_q(b, qv1);
+                    store_q(qv1, sm.qs[w][0]);
+                }
+                float(*qs)[DD + 4] = sm.qs[w][qb];
                 wave_sync();
                 const int d = (b + 1) * DD;
                 const float cf = coef[b];
@@ -162,6 +194,12 @@ __global__ __launch_bounds__(64 * SCAN_WAVES) __attribute__((amdgpu_waves_per_eu
                             }
                         }
                     }
+                }
+                if constexpr (PF) {
+                    store_q(qv1, sm.qs[w][qb ^ 1]);
+                    qb ^= 1;
+#pragma unroll
+                    for (int k = 0; k < DD; ++k) o[k] = o1[k];
                 }
                 wave_sync();
                 if (d >= D) break;
@@ -277,41 +315,44 @@ size_t scan_smem_bytes(int nb, int kcap) {
 }
 
 template <int DT, int DD, int QW>
-hipError_t launch_scan_t(const ScanArgs &a, int grid, hipStream_t s) {
+hipError_t launch_scan_t(const ScanArgs &a, int grid, bool pf, hipStream_t s) {
     size_t sh = scan_smem_bytes<DD, QW>(a.nb, a.kcap);
     if (sh > 64 * 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((scan_kernel<DT, DD, QW>), dim3(grid), dim3(64 * SCAN_WAVES), sh, s, a);
+    if (pf)
+        hipLaunchKernelGGL((scan_kernel<DT, DD, QW, true>), dim3(grid), dim3(64 * SCAN_WAVES), sh, s, a);
+    else
+        hipLaunchKernelGGL((scan_kernel<DT, DD, QW, false>), dim3(grid), dim3(64 * SCAN_WAVES), sh, s, a);
     return hipGetLastError();
 }
 
 template <int DT, int DD>
-hipError_t launch_scan_q(const ScanArgs &a, int qw, int grid, hipStream_t s) {
+hipError_t launch_scan_q(const ScanArgs &a, int qw, int grid, bool pf, hipStream_t s) {
     switch (qw) {
-        case 16: return launch_scan_t<DT, DD, 16>(a, grid, s);
-        case 8: return launch_scan_t<DT, DD, 8>(a, grid, s);
-        case 4: return launch_scan_t<DT, DD, 4>(a, grid, s);
-        case 2: return launch_scan_t<DT, DD, 2>(a, grid, s);
-        case 1: return launch_scan_t<DT, DD, 1>(a, grid, s);
+        case 16: return launch_scan_t<DT, DD, 16>(a, grid, pf, s);
+        case 8: return launch_scan_t<DT, DD, 8>(a, grid, pf, s);
+        case 4: return launch_scan_t<DT, DD, 4>(a, grid, pf, s);
+        case 2: return launch_scan_t<DT, DD, 2>(a, grid, pf, s);
+        case 1: return launch_scan_t<DT, DD, 1>(a, grid, pf, s);
     }
     return hipErrorInvalidValue;
 }
 
 template <int DT>
-hipError_t launch_scan_d(const ScanArgs &a, int dd, int qw, int grid, hipStream_t s) {
+hipError_t launch_scan_d(const ScanArgs &a, int dd, int qw, int grid, bool pf, hipStream_t s) {
     switch (dd) {
-        case 8: return launch_scan_q<DT, 8>(a, qw, grid, s);
-        case 16: return launch_scan_q<DT, 16>(a, qw, grid, s);
-        case 32: return launch_scan_q<DT, 32>(a, qw, grid, s);
-        case 64: return launch_scan_q<DT, 64>(a, qw, grid, s);
+        case 8: return launch_scan_q<DT, 8>(a, qw, grid, pf, s);
+        case 16: return launch_scan_q<DT, 16>(a, qw, grid, pf, s);
+        case 32: return launch_scan_q<DT, 32>(a, qw, grid, pf, s);
+        case 64: return launch_scan_q<DT, 64>(a, qw, grid, pf, s);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_scan(const ScanArgs &a, int dtype, int dd, int qw, int grid, hipStream_t s) {
+hipError_t launch_scan(const ScanArgs &a, int dtype, int dd, int qw, int grid, bool pf, hipStream_t s) {
     switch (dtype) {
-        case ADS_F32: return launch_scan_d<ADS_F32>(a, dd, qw, grid, s);
-        case ADS_BF16: return launch_scan_d<ADS_BF16>(a, dd, qw, grid, s);
-        case ADS_F16: return launch_scan_d<ADS_F16>(a, dd, qw, grid, s);
+        case ADS_F32: return launch_scan_d<ADS_F32>(a, dd, qw, grid, pf, s);
+        case ADS_BF16: return launch_scan_d<ADS_BF16>(a, dd, qw, grid, pf, s);
+        case ADS_F16: return launch_scan_d<ADS_F16>(a, dd, qw, grid, pf, s);
     }
     return hipErrorInvalidValue;
 }

@@ -90,8 +90,17 @@ __device__ __forceinline__ void load_run(const unsigned char *p, float *out) {
     }
 }
 
+// Number of set bits of a 16-bit per-lane mask summed over the wave, with
+// ballots (no cross-lane data movement through LDS).
+__device__ __forceinline__ int wave_count16(uint32_t bits) {
+    int n = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) n += __popcll(__ballot((bits >> k) & 1u));
+    return n;
+}
+
 template <int DT, int DD, int QW>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void scan_mfma_kernel(ScanArgs a) {
+__global__ __launch_bounds__(64) void scan_mfma_kernel(ScanArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     MfmaSmem<QW> &sm = *reinterpret_cast<MfmaSmem<QW> *>(smem_raw);
     float *coef = reinterpret_cast<float *>(smem_raw + sizeof(MfmaSmem<QW>));
@@ -189,22 +198,34 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void sc
                     if (vok && qok[i]) alive |= 1u << (4 * t + i);
                 }
             }
-            const int tile_pairs = wave_sum(__popc(alive));
+            const int tile_pairs = wave_count16(alive);
             int nexq = 0, m = 0, b = 0;
             bool handoff = false;
-            for (; tile_pairs > 0 && b < nb; ++b) {
-                // Loads are unconditional: a slot past qc reads slot 0's row and a
-                // vector past the list end reads the list's last vector; their C
-                // rows / columns belong to pairs that are never alive.
-                float av[KS];
-                load_run<ADS_F32, KS>(reinterpret_cast<const unsigned char *>(qr + b * DD), av);
-#pragma unroll
-                for (int j = 0; j < KS; ++j) av[j] *= -2.f;
-                // the norm step: k-slot 0 carries (||q_b||^2, 1), k-slot 1 (1, ||o_b||^2)
-                const float ax = g == 0 ? qb[b] : (g == 1 ? 1.f : 0.f);
+            // Operands of one block.  Loads are unconditional: a slot past qc
+            // reads slot 0's row and a vector past the list end reads the
+            // list's last vector; their C rows / columns belong to pairs that
+            // are never alive.  The next block's operands are fetched before
+            // the current block is evaluated (the tile almost always needs it).
+            float av[KS], bo[4][KS], on[4], qbv;
+            auto fetch = [&](int bb, float *av_, float (*bo_)[KS], float *on_, float &qbv_) {
+                load_run<ADS_F32, KS>(reinterpret_cast<const unsigned char *>(qr + bb * DD), av_);
+                qbv_ = qb[bb];
                 // wave-uniform bases, 32-bit lane offsets
-                const unsigned char *bblk = lbase + (int64_t)b * nl * (DD * EB);
-                const float *bnb = bnl + (int64_t)b * nl;
+                const unsigned char *bblk = lbase + (int64_t)bb * nl * (DD * EB);
+                const float *bnb = bnl + (int64_t)bb * nl;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int vr = min(vc + 16 * t + n16, nl - 1);     // clamped list row
+                    load_run<DT, KS>(bblk + (uint32_t)(vr * (DD * EB) + g * (KS * EB)), bo_[t]);
+                    on_[t] = bnb[(uint32_t)vr];
+                }
+            };
+            if (tile_pairs > 0) fetch(0, av, bo, on, qbv);
+            for (; tile_pairs > 0 && b < nb; ++b) {
+                float av1[KS], bo1[4][KS], on1[4], qbv1;
+                fetch(b + 1 < nb ? b + 1 : b, av1, bo1, on1, qbv1);
+                // the norm step: k-slot 0 carries (||q_b||^2, 1), k-slot 1 (1, ||o_b||^2)
+                const float ax = g == 0 ? qbv : (g == 1 ? 1.f : 0.f);
                 const int d = (b + 1) * DD;
                 const bool last = d >= D;
                 // at d < D: reject above coef(d) r^2, keep at or below it; at
@@ -216,15 +237,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void sc
                 uint32_t rb = 0, kb = 0;
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    // one 16-vector slice at a time keeps the live operands small
-                    const int vr = min(vc + 16 * t + n16, nl - 1);     // clamped list row
-                    float bo[KS];
-                    load_run<DT, KS>(bblk + (uint32_t)(vr * (DD * EB) + g * (KS * EB)), bo);
-                    const float onv = bnb[(uint32_t)vr];
-                    const float bx = g == 0 ? 1.f : (g == 1 ? onv : 0.f);
+                    const float bx = g == 0 ? 1.f : (g == 1 ? on[t] : 0.f);
                     v4f c = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                    for (int j = 0; j < KS; ++j) c = __builtin_amdgcn_mfma_f32_16x16x4f32(av[j], bo[j], c, 0, 0, 0);
+                    for (int j = 0; j < KS; ++j)
+                        c = __builtin_amdgcn_mfma_f32_16x16x4f32(-2.f * av[j], bo[t][j], c, 0, 0, 0);
                     c = __builtin_amdgcn_mfma_f32_16x16x4f32(ax, bx, c, 0, 0, 0);
                     const float vmt = sm.vmarg[16 * t + n16];
 #pragma unroll
@@ -254,7 +271,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void sc
                     }
                     nexq += tot;
                 }
-                const int na = wave_sum(__popc(alive));
+                const int na = wave_count16(alive);
                 if (na == 0 || last) break;
                 if ((float)na <= a.dense_frac * (float)tile_pairs) {
                     const int ln = opaque(lane);
@@ -270,6 +287,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void sc
                     ++b;
                     break;
                 }
+#pragma unroll
+                for (int j = 0; j < KS; ++j) av[j] = av1[j];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    on[t] = on1[t];
+#pragma unroll
+                    for (int j = 0; j < KS; ++j) bo[t][j] = bo1[t][j];
+                }
+                qbv = qbv1;
             }
             wave_sync();
             auto no_sink = [](int, float, int) {};

@@ -4,7 +4,7 @@
 // A list holds (vector of the current 64-vector tile, query of the unit)
 // pairs that all stand at the same next block bcur, each with its partial
 // squared distance S over blocks [0, bcur).  With n pairs left, each pair
-// takes G = 64 / n lanes (a power of two) that evaluate blocks
+// takes G = min(16, 64 / n) lanes (a power of two) that evaluate blocks
 // bcur .. bcur+G-1 at once; an in-group scan gives S at every block boundary
 // and the first deciding block is found with a ballot, so the decisions are
 // those of testing block by block (Algorithm 1, one hypothesis test per
@@ -81,6 +81,12 @@ __device__ __forceinline__ float block_partial(const unsigned char *op, const fl
     return s;
 }
 
+// x of the previous lane within each row of 16 lanes (DPP row_shr:1); the
+// first lane of a row gets 0.
+__device__ __forceinline__ float row_shr1(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x111, 0xf, 0xf, true));
+}
+
 // List entry: S bits (high word) | query slot << 6 | vector of the tile.
 __device__ __forceinline__ uint64_t pair_entry(float s, int jj, int vv) {
     return ((uint64_t)__float_as_uint(s) << 32) | (uint32_t)(jj << 6 | vv);
@@ -121,8 +127,10 @@ __device__ __forceinline__ SparseOut sparse_run(const SparseCtx &c, uint64_t *li
     int cur = 0;
     while (n > 0 && bcur < nb) {
         wave_sync();
+        // lanes per pair: a power of two up to 16, so that a group never
+        // crosses a DPP row
         int G = 1;
-        while (G * 2 * n <= 64 && G * 2 <= nb - bcur) G *= 2;
+        while (G < 16 && G * 2 * n <= 64 && G * 2 <= nb - bcur) G *= 2;
         const int ppr = 64 / G;                 // pairs per round
         const int gi = lane & (G - 1);
         const uint64_t *src = cur ? list1 : list0;
@@ -145,7 +153,7 @@ __device__ __forceinline__ SparseOut sparse_run(const SparseCtx &c, uint64_t *li
             // independent of G): one lane of the group per round
             float sb = gi == 0 ? s0 + part : 0.f;
             for (int t = 1; t < G; ++t) {
-                const float prev = __shfl_up(sb, 1, G);
+                const float prev = row_shr1(sb);
                 if (gi == t) sb = prev + part;
             }
             const int d = (blk + 1) * DD;
@@ -171,7 +179,7 @@ __device__ __forceinline__ SparseOut sparse_run(const SparseCtx &c, uint64_t *li
             }
             const uint64_t rm = __ballot(ev);
             const uint64_t um = __ballot(unc);
-            const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (lane & ~(G - 1)));
+            const uint64_t gmask = ((1ull << G) - 1ull) << (lane & ~(G - 1));
             const uint64_t grm = rm & gmask;
             // the group's last block and the value of S there
             const int glast = min(G, nb - bcur) - 1;
