@@ -189,6 +189,7 @@ __global__ __launch_bounds__(64) void scan_mfma_kernel(ScanArgs a) {
             for (int i = 0; i < 4; ++i) r2v[i] = qok[i] ? sm.r2s[4 * g + i] : 0.f;
             float S[4][4];
             uint32_t alive = 0;         // bit 4t+i: pair (vector 16t + n16, query slot 4g + i)
+            uint32_t nothr = 0;         // pairs of slots without a threshold yet (r = +inf)
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const bool vok = vc + 16 * t + n16 < nl;
@@ -196,6 +197,7 @@ __global__ __launch_bounds__(64) void scan_mfma_kernel(ScanArgs a) {
                 for (int i = 0; i < 4; ++i) {
                     S[t][i] = 0.f;
                     if (vok && qok[i]) alive |= 1u << (4 * t + i);
+                    if (__builtin_isinf(r2v[i])) nothr |= 1u << (4 * t + i);
                 }
             }
             const int tile_pairs = wave_count16(alive);
@@ -254,7 +256,10 @@ __global__ __launch_bounds__(64) void scan_mfma_kernel(ScanArgs a) {
                         kb |= (dl <= -mg ? 1u : 0u) << (4 * t + i);
                     }
                 }
+                // nothing is kept at d = D; a query without a threshold accepts
+                // every candidate, so its pairs go to the exact queue at once
                 if (last) kb = 0u;
+                kb &= ~nothr;
                 uint32_t ub = ~(rb | kb);
                 rb &= alive;
                 ub &= alive;
