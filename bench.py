@@ -213,7 +213,8 @@ def main() -> int:
     achieved_gbs = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
     flops = 3.0 * dims  # one subtract and one fused multiply-add per sampled coordinate
     achieved_tflops = flops / (scan_ms_step * 1e-3) / 1e12
-    traffic = scan_traffic_from_profile()
+    scan_kernel = "scan_mfma_kernel" if args.dense_mfma else "scan_kernel"
+    traffic = scan_traffic_from_profile(scan_kernel)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -245,7 +246,7 @@ def main() -> int:
         "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3),
                      "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved_tflops / FP32_VALU_PEAK_TFLOPS, 4),
-                     "traffic": traffic, "kernel": "scan_kernel",
+                     "traffic": traffic, "kernel": scan_kernel,
                      "avg_launch_ms": round(avg_launch_ms, 4),
                      "launches_per_step": launches_per_step,
                      "alg_flops_per_launch": round(flops / max(1.0, launches_per_step), 1)},
@@ -301,14 +302,28 @@ def serve(args, w, ix, q, gt, x):
     return 0
 
 
-def scan_traffic_from_profile():
-    """HBM bytes per scan launch from the committed counter summary, or None
-    when the scan kernel source changed since the counters were taken."""
+# Sources the scan kernels are compiled from (the counter summary records
+# their digest; a changed kernel invalidates the traffic figure).
+SCAN_SOURCES = {
+    "scan_kernel": ["scan.hip", "scan_sparse.h", "common.h", "kernels.h"],
+    "scan_mfma_kernel": ["scan_mfma.hip", "scan_sparse.h", "common.h", "kernels.h"],
+}
+
+
+def scan_source_sha(kernel: str = "scan_kernel") -> str:
     import hashlib
-    prof = os.path.join(ROOT, "profiles", "scan_kernel_ivf_d960_counters.txt")
-    src = os.path.join(ROOT, "paper_2303_09855_amd", "csrc", "scan.hip")
+    h = hashlib.sha256()
+    for f in SCAN_SOURCES[kernel]:
+        h.update(open(os.path.join(ROOT, "paper_2303_09855_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def scan_traffic_from_profile(kernel: str = "scan_kernel"):
+    """HBM bytes per scan launch from the committed counter summary, or None
+    when the scan kernel sources changed since the counters were taken."""
+    prof = os.path.join(ROOT, "profiles", f"{kernel}_ivf_d960_counters.txt")
     try:
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        sha = scan_source_sha(kernel)
         fields = {}
         for line in open(prof):
             if ":" in line:
