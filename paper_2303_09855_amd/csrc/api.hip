@@ -168,6 +168,13 @@ constexpr int KCAP_MAX = 512;
 #define ADS_PREFETCH_UNITS 8192
 #endif
 constexpr int64_t PREFETCH_UNITS = ADS_PREFETCH_UNITS;
+// The first sweeps update thresholds once per round of four tiles (the
+// register scan runs them with four waves per unit): more parallel work in
+// the sweeps that have few units.
+#ifndef ADS_WIDE_SWEEPS
+#define ADS_WIDE_SWEEPS 2
+#endif
+constexpr int WIDE_SWEEPS = ADS_WIDE_SWEEPS;
 constexpr int NPROBE_MAX_LIMIT = 8192;
 
 struct SearchLayout {
@@ -710,6 +717,7 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
         a.D = D;
         a.nb = ix->nb;
         a.dense_frac = g_tune.dense_frac;
+        a.round_tiles = s < WIDE_SWEEPS ? 4 : 1;
         a.blk_norm = ix->blk_norm;
         a.vec_norm = ix->vec_norm;
         a.qbn = reinterpret_cast<const float *>(ws + L.off_qbn);
@@ -726,7 +734,8 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
             if (L.mfma)
                 SEARCH_TRY(launch_scan_mfma(a, ix->storage, ix->dd, qw, (int)(8 * P), stream), "scan");
             else
-                SEARCH_TRY(launch_scan(a, ix->storage, ix->dd, qw, (int)(8 * P), units_bound < PREFETCH_UNITS, stream), "scan");
+                SEARCH_TRY(launch_scan(a, ix->storage, ix->dd, qw, (int)(8 * P), units_bound < PREFETCH_UNITS,
+                                       a.round_tiles == 4, stream), "scan");
         }
         const size_t sh = sizeof(uint64_t) * (size_t)next_pow2(L.kcap);
         PhaseTimer tm(ADS_PHASE_MERGE, stream);

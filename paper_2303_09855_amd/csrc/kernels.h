@@ -24,6 +24,7 @@ struct ScanArgs {
     int method;
     int nprobe_max, kcap, D, nb;
     float dense_frac;       // pairs alive at or below this fraction (<= 0.25) switch to the pair list
+    int round_tiles;        // 64-vector tiles per threshold update (4 in the first sweeps, else 1)
     // matrix-core scan only
     const float *blk_norm;  // per list [nb][nl]: squared norm of each stored block
     const float *vec_norm;  // [n] squared norm of each stored vector, by position
@@ -31,7 +32,8 @@ struct ScanArgs {
     float kappa;            // margin factor of the dot-product form
 };
 
-hipError_t launch_scan(const ScanArgs &a, int dtype, int dd, int qw, int grid, bool prefetch, hipStream_t s);
+hipError_t launch_scan(const ScanArgs &a, int dtype, int dd, int qw, int grid, bool prefetch, bool wide,
+                       hipStream_t s);
 hipError_t launch_scan_mfma(const ScanArgs &a, int dtype, int dd, int qw, int grid, hipStream_t s);
 float scan_margin_kappa(int dd, int nb);
 

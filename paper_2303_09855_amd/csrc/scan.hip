@@ -33,16 +33,16 @@
 
 namespace ads {
 
-constexpr int SCAN_WAVES = 1;    // waves per workgroup; each takes one 64-vector slice per round
-
-template <int DD, int QW>
+// W waves per workgroup: each takes one 64-vector tile per round, and the
+// round's positives lower the thresholds before the next round.
+template <int DD, int QW, int W>
 struct ScanSmem {
     static constexpr int LCAP = 16 * QW;   // pairs alive when the dense phase hands over (<= 1/4)
     // wave-private
-    float qs[SCAN_WAVES][2][QW][DD + 4];     // query block, double-buffered
-    uint64_t list[SCAN_WAVES][2][LCAP];
-    uint64_t pos[SCAN_WAVES][QW][64];
-    int pcnt[SCAN_WAVES][QW];
+    float qs[W][2][QW][DD + 4];     // query block, double-buffered
+    uint64_t list[W][2][LCAP];
+    uint64_t pos[W][QW][64];
+    int pcnt[W][QW];
     // shared by the unit
     float r2s[QW];
     int qidx[QW], qrank[QW], qk[QW], tkcnt[QW], tkmax[QW];
@@ -51,13 +51,13 @@ struct ScanSmem {
 
 // PF: fetch the next block of the dense phase while the current one is
 // evaluated (more registers; for sweeps with fewer units than wave slots).
-template <int DT, int DD, int QW, bool PF>
-__global__ __launch_bounds__(64 * SCAN_WAVES) __attribute__((amdgpu_waves_per_eu(PF ? 2 : 4))) void scan_kernel(ScanArgs a) {
+template <int DT, int DD, int QW, bool PF, int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(PF ? 2 : 4))) void scan_kernel(ScanArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    ScanSmem<DD, QW> &sm = *reinterpret_cast<ScanSmem<DD, QW> *>(smem_raw);
-    float *coef = reinterpret_cast<float *>(smem_raw + sizeof(ScanSmem<DD, QW>));
+    ScanSmem<DD, QW, W> &sm = *reinterpret_cast<ScanSmem<DD, QW, W> *>(smem_raw);
+    float *coef = reinterpret_cast<float *>(smem_raw + sizeof(ScanSmem<DD, QW, W>));
     uint64_t *tk = reinterpret_cast<uint64_t *>(
-        smem_raw + ((sizeof(ScanSmem<DD, QW>) + sizeof(float) * a.nb + 15) & ~(size_t)15));
+        smem_raw + ((sizeof(ScanSmem<DD, QW, W>) + sizeof(float) * a.nb + 15) & ~(size_t)15));
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int x = blockIdx.x & 7;
@@ -69,7 +69,7 @@ __global__ __launch_bounds__(64 * SCAN_WAVES) __attribute__((amdgpu_waves_per_eu
     const uint64_t lanemask_lt = (1ull << lane) - 1ull;
     int *pcnt = sm.pcnt[w];
 
-    for (int b = tid; b < nb; b += 64 * SCAN_WAVES) {
+    for (int b = tid; b < nb; b += 64 * W) {
         int d = (b + 1) * DD;
         coef[b] = d < D ? test_coef(d, D, a.eps0, a.method) : 0.f;
     }
@@ -101,7 +101,9 @@ __global__ __launch_bounds__(64 * SCAN_WAVES) __attribute__((amdgpu_waves_per_eu
             my_dcos += (unsigned long long)act * (unsigned long long)nl;
         }
 
-        for (int r0 = 0; r0 < nl; r0 += 64 * SCAN_WAVES) {
+        for (int r0 = 0; r0 < nl; r0 += 64 * W) {
+            // thresholds change only at the end of a round of round_tiles tiles
+            const bool round_end = ((r0 / 64 + W) % a.round_tiles) == 0 || r0 + 64 * W >= nl;
             // ---- this wave's slice: vectors [vc, vc + 64) ----
             const int vc = r0 + w * 64;
             if (lane < QW) pcnt[lane] = 0;
@@ -257,7 +259,7 @@ __global__ __launch_bounds__(64 * SCAN_WAVES) __attribute__((amdgpu_waves_per_eu
                 const int j = tid, K = sm.qk[j];
                 uint64_t *mytk = tk + (int64_t)j * kcap;
                 int c = sm.tkcnt[j], mx = sm.tkmax[j];
-                for (int ww = 0; ww < SCAN_WAVES; ++ww) {
+                for (int ww = 0; ww < W; ++ww) {
                     const int np = sm.pcnt[ww][j];
                     for (int p = 0; p < np; ++p) {
                         const uint64_t key = sm.pos[ww][j][p];
@@ -276,7 +278,7 @@ __global__ __launch_bounds__(64 * SCAN_WAVES) __attribute__((amdgpu_waves_per_eu
                 }
                 sm.tkcnt[j] = c;
                 sm.tkmax[j] = mx;
-                if (c == K) {
+                if (round_end && c == K) {
                     const float kth = key_dist2(mytk[mx]);
                     if (kth < sm.r2s[j]) sm.r2s[j] = kth;
                 }
@@ -284,7 +286,7 @@ __global__ __launch_bounds__(64 * SCAN_WAVES) __attribute__((amdgpu_waves_per_eu
             __syncthreads();
         }
         // publish the unit's per-query KNN sets for the merge
-        for (int i = tid; i < qc * kcap; i += 64 * SCAN_WAVES) {
+        for (int i = tid; i < qc * kcap; i += 64 * W) {
             const int j = i / kcap, t = i % kcap;
             const uint64_t key = (sm.qk[j] > 0 && t < sm.tkcnt[j]) ? tk[(int64_t)j * kcap + t] : KEY_NONE;
             a.slots[((int64_t)sm.qidx[j] * a.nprobe_max + sm.qrank[j]) * kcap + t] = key;
@@ -307,52 +309,63 @@ __global__ __launch_bounds__(64 * SCAN_WAVES) __attribute__((amdgpu_waves_per_eu
     }
 }
 
-template <int DD, int QW>
+template <int DD, int QW, int W>
 size_t scan_smem_bytes(int nb, int kcap) {
-    size_t s = sizeof(ScanSmem<DD, QW>) + sizeof(float) * nb;
+    size_t s = sizeof(ScanSmem<DD, QW, W>) + sizeof(float) * nb;
     s = (s + 15) & ~(size_t)15;
     return s + sizeof(uint64_t) * (size_t)QW * kcap;
 }
 
+// Three forms: one wave per unit (plain or prefetching) and four waves per
+// unit (rounds of four tiles).
 template <int DT, int DD, int QW>
-hipError_t launch_scan_t(const ScanArgs &a, int grid, bool pf, hipStream_t s) {
-    size_t sh = scan_smem_bytes<DD, QW>(a.nb, a.kcap);
+hipError_t launch_scan_t(const ScanArgs &a, int grid, bool pf, bool wide, hipStream_t s) {
+    // rounds of four tiles on four waves when the LDS fits, else on one wave
+    // (same thresholds, same results)
+    if (wide && a.round_tiles == 4) {
+        const size_t sh = scan_smem_bytes<DD, QW, 4>(a.nb, a.kcap);
+        if (sh <= 64 * 1024) {
+            hipLaunchKernelGGL((scan_kernel<DT, DD, QW, false, 4>), dim3(grid), dim3(256), sh, s, a);
+            return hipGetLastError();
+        }
+    }
+    const size_t sh = scan_smem_bytes<DD, QW, 1>(a.nb, a.kcap);
     if (sh > 64 * 1024) return hipErrorInvalidValue;
     if (pf)
-        hipLaunchKernelGGL((scan_kernel<DT, DD, QW, true>), dim3(grid), dim3(64 * SCAN_WAVES), sh, s, a);
+        hipLaunchKernelGGL((scan_kernel<DT, DD, QW, true, 1>), dim3(grid), dim3(64), sh, s, a);
     else
-        hipLaunchKernelGGL((scan_kernel<DT, DD, QW, false>), dim3(grid), dim3(64 * SCAN_WAVES), sh, s, a);
+        hipLaunchKernelGGL((scan_kernel<DT, DD, QW, false, 1>), dim3(grid), dim3(64), sh, s, a);
     return hipGetLastError();
 }
 
 template <int DT, int DD>
-hipError_t launch_scan_q(const ScanArgs &a, int qw, int grid, bool pf, hipStream_t s) {
+hipError_t launch_scan_q(const ScanArgs &a, int qw, int grid, bool pf, bool wide, hipStream_t s) {
     switch (qw) {
-        case 16: return launch_scan_t<DT, DD, 16>(a, grid, pf, s);
-        case 8: return launch_scan_t<DT, DD, 8>(a, grid, pf, s);
-        case 4: return launch_scan_t<DT, DD, 4>(a, grid, pf, s);
-        case 2: return launch_scan_t<DT, DD, 2>(a, grid, pf, s);
-        case 1: return launch_scan_t<DT, DD, 1>(a, grid, pf, s);
+        case 16: return launch_scan_t<DT, DD, 16>(a, grid, pf, wide, s);
+        case 8: return launch_scan_t<DT, DD, 8>(a, grid, pf, wide, s);
+        case 4: return launch_scan_t<DT, DD, 4>(a, grid, pf, wide, s);
+        case 2: return launch_scan_t<DT, DD, 2>(a, grid, pf, wide, s);
+        case 1: return launch_scan_t<DT, DD, 1>(a, grid, pf, wide, s);
     }
     return hipErrorInvalidValue;
 }
 
 template <int DT>
-hipError_t launch_scan_d(const ScanArgs &a, int dd, int qw, int grid, bool pf, hipStream_t s) {
+hipError_t launch_scan_d(const ScanArgs &a, int dd, int qw, int grid, bool pf, bool wide, hipStream_t s) {
     switch (dd) {
-        case 8: return launch_scan_q<DT, 8>(a, qw, grid, pf, s);
-        case 16: return launch_scan_q<DT, 16>(a, qw, grid, pf, s);
-        case 32: return launch_scan_q<DT, 32>(a, qw, grid, pf, s);
-        case 64: return launch_scan_q<DT, 64>(a, qw, grid, pf, s);
+        case 8: return launch_scan_q<DT, 8>(a, qw, grid, pf, wide, s);
+        case 16: return launch_scan_q<DT, 16>(a, qw, grid, pf, wide, s);
+        case 32: return launch_scan_q<DT, 32>(a, qw, grid, pf, wide, s);
+        case 64: return launch_scan_q<DT, 64>(a, qw, grid, pf, wide, s);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_scan(const ScanArgs &a, int dtype, int dd, int qw, int grid, bool pf, hipStream_t s) {
+hipError_t launch_scan(const ScanArgs &a, int dtype, int dd, int qw, int grid, bool pf, bool wide, hipStream_t s) {
     switch (dtype) {
-        case ADS_F32: return launch_scan_d<ADS_F32>(a, dd, qw, grid, pf, s);
-        case ADS_BF16: return launch_scan_d<ADS_BF16>(a, dd, qw, grid, pf, s);
-        case ADS_F16: return launch_scan_d<ADS_F16>(a, dd, qw, grid, pf, s);
+        case ADS_F32: return launch_scan_d<ADS_F32>(a, dd, qw, grid, pf, wide, s);
+        case ADS_BF16: return launch_scan_d<ADS_BF16>(a, dd, qw, grid, pf, wide, s);
+        case ADS_F16: return launch_scan_d<ADS_F16>(a, dd, qw, grid, pf, wide, s);
     }
     return hipErrorInvalidValue;
 }

@@ -179,6 +179,8 @@ __global__ __launch_bounds__(64) void scan_mfma_kernel(ScanArgs a) {
 
         for (int vc = 0; vc < nl; vc += 64) {
             ctx.vc = vc;
+            // thresholds change only at the end of a round of round_tiles tiles
+            const bool round_end = ((vc >> 6) + 1) % a.round_tiles == 0 || vc + 64 >= nl;
             {
                 const int v = vc + lane;
                 sm.vmarg[lane] = v < nl ? a.kappa * a.vec_norm[off + v] : 0.f;
@@ -351,8 +353,8 @@ __global__ __launch_bounds__(64) void scan_mfma_kernel(ScanArgs a) {
                 }
             }
             wave_sync();
-            // the tile's positives lower the thresholds for the next tile
-            if (lane < qc && sm.qk[lane] > 0 && sm.tkcnt[lane] == sm.qk[lane]) {
+            // the round's positives lower the thresholds for the next round
+            if (round_end && lane < qc && sm.qk[lane] > 0 && sm.tkcnt[lane] == sm.qk[lane]) {
                 const float kth = key_dist2(tk[(int64_t)lane * kcap + sm.tkmax[lane]]);
                 if (kth < sm.r2s[lane]) sm.r2s[lane] = kth;
             }
