@@ -70,6 +70,8 @@ def parse():
     ap.add_argument("--dense-mfma", type=int, default=0, choices=[0, 1],
                     help="ADSampling scan variant: 1 = dense phase on the matrix cores, "
                          "0 = register-dense phase (default; same results)")
+    ap.add_argument("--tune", default="",
+                    help="scan scheduling knobs, e.g. sweep_log2=4,dense_frac=0.25 (ads_tuning fields)")
     ap.add_argument("--nprobe", type=int, default=None,
                     help="use this nprobe for both methods instead of searching for the "
                          "smallest one that reaches the target recall")
@@ -102,7 +104,11 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     ads.load()
-    ads.set_tuning(dense_mfma=args.dense_mfma)
+    knobs = {"dense_mfma": args.dense_mfma}
+    for kv in filter(None, args.tune.split(",")):
+        k, v = kv.split("=")
+        knobs[k.strip()] = float(v) if k.strip() == "dense_frac" else int(v)
+    ads.set_tuning(**knobs)
     w = sd.WORKLOADS[args.workload]
     if args.nq or args.n:
         w = w.scaled(nq=args.nq or w.nq, n=args.n or w.n)

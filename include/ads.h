@@ -305,7 +305,7 @@ typedef struct {
                                  power of two up to 8 (16 with dense_mfma) whose KNN sets fit
                                  in 4 KB of LDS.  Default 0. */
     int32_t sweep_log2;       /* probe ranks are scanned in sweeps [0,1), [1,g), [g,g^2), ...
-                                 with g = 2^sweep_log2, sweep_log2 in [1, 6].  Default 3. */
+                                 with g = 2^sweep_log2, sweep_log2 in [1, 6].  Default 4. */
     int32_t grid_per_xcd;     /* persistent scan workgroups per XCD, 0 = as many as the
                                  sweep has units (capped at 4096).  Default 0. */
     int32_t dense_mfma;       /* 1: ADSampling / PDScanning scans evaluate the dense phase in

@@ -34,7 +34,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ads_mi355x", "t
 KNOB_CHOICES = {
     "queries_per_unit": [4, 8, 16],
     "dense_frac": [0.0625, 0.125, 0.25],
-    "sweep_log2": [2, 3, 4],
+    "sweep_log2": [3, 4, 5],
     "grid_per_xcd": [0, 512, 2048],
 }
 

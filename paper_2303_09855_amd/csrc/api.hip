@@ -60,7 +60,7 @@ struct ads_index {
 namespace {
 
 thread_local std::string g_err;
-thread_local ads_tuning g_tune = {0.125f, 0, 3, 0, 0};
+thread_local ads_tuning g_tune = {0.125f, 0, 4, 0, 0};
 
 // Per-thread event profiler (ads_profile_enable / ads_profile_collect).
 struct Profiler {

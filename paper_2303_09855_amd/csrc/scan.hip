@@ -3,7 +3,8 @@
 // (query, list) pairs by list, per-query merges and the final output.
 //
 // Schedule.  The probe ranks of every query are cut into sweeps
-// [0,1), [1,4), [4,16), [16,64), ...  Each sweep is one list-major launch:
+// [0,1), [1,g), [g,g^2), ... (g = 2^sweep_log2, 16 by default).  Each sweep
+// is one list-major launch:
 // the (query, rank) pairs of the sweep are grouped by list, and a unit of work
 // is one list with up to QW of the queries that probe it, so a list's vectors
 // are fetched from HBM about once per sweep and reused by all its queries.
