@@ -9,7 +9,10 @@ GPU start as soon as a slot and memory free up.  The index stays resident.
 
 A query's result does not depend on the other queries of its batch (the
 search is batch independent), so a request gets the same answer alone and in
-the mix.
+the mix.  Requests wait in one queue per K class (K rounded up to a power of
+two): a batch's KNN-set capacity follows its largest K, so mixing K = 10 with
+K = 100 would run the K = 10 requests with 100-entry sets and fewer queries
+per scan unit.  The class whose oldest request arrived first is served next.
 """
 
 from __future__ import annotations
@@ -84,16 +87,27 @@ class Server:
         self.admission = AdmissionController(budget, max_batch, n_streams)
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
 
-    def batch_bytes(self, n: int) -> int:
+    def batch_bytes(self, n: int, k_max: int | None = None, nprobe_max: int | None = None) -> int:
         if n <= 0:
             return 0
-        ws = B.search_workspace_size(self.index, n, self.k_max, self.nprobe_max, self.rerank)
-        return ws + 256 + n * (self.D * 4 + 8 + self.k_max * 12)
+        k_max = self.k_max if k_max is None else k_max
+        nprobe_max = self.nprobe_max if nprobe_max is None else nprobe_max
+        ws = B.search_workspace_size(self.index, n, k_max, nprobe_max, self.rerank)
+        return ws + 256 + n * (self.D * 4 + 8 + k_max * 12)
+
+    @staticmethod
+    def k_class(K: int) -> int:
+        c = 1
+        while c < K:
+            c *= 2
+        return c
 
     def _launch(self, reqs, stream):
         torch = self.torch
         n = len(reqs)
-        nbytes = self.batch_bytes(n)
+        k_max = max(r.K for r in reqs)
+        np_max = max(r.nprobe for r in reqs)
+        nbytes = self.batch_bytes(n, k_max, np_max)
         with torch.cuda.stream(stream):
             hq = torch.from_numpy(np.stack([r.q for r in reqs]).astype(np.float32)).pin_memory()
             hk = torch.tensor([r.K for r in reqs], dtype=torch.int32).pin_memory()
@@ -103,14 +117,14 @@ class Server:
             npb = hp.to("cuda", non_blocking=True)
             ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
             off = (-ws.data_ptr()) % 256
-            ids = torch.empty((n, self.k_max), dtype=torch.int64, device="cuda")
-            dist = torch.empty((n, self.k_max), dtype=torch.float32, device="cuda")
+            ids = torch.empty((n, k_max), dtype=torch.int64, device="cuda")
+            dist = torch.empty((n, k_max), dtype=torch.float32, device="cuda")
             B._check(B.load().ads_search(
-                self.index.handle, B._ptr(q), n, B._ptr(K), B._ptr(npb), self.k_max, self.nprobe_max,
+                self.index.handle, B._ptr(q), n, B._ptr(K), B._ptr(npb), k_max, np_max,
                 float(self.eps0), B.ADSAMPLING, self.rerank, B._ptr(ids), B._ptr(dist), None, None,
                 B.ctypes.c_void_p(ws.data_ptr() + off), B.ctypes.c_void_p(stream.cuda_stream)))
-            h_ids = torch.empty((n, self.k_max), dtype=torch.int64).pin_memory()
-            h_dist = torch.empty((n, self.k_max), dtype=torch.float32).pin_memory()
+            h_ids = torch.empty((n, k_max), dtype=torch.int64).pin_memory()
+            h_dist = torch.empty((n, k_max), dtype=torch.float32).pin_memory()
             h_ids.copy_(ids, non_blocking=True)
             h_dist.copy_(dist, non_blocking=True)
             ev = torch.cuda.Event()
@@ -121,7 +135,10 @@ class Server:
         """Serve requests (sorted by arrival).  Returns (results {rid: (ids, dist)},
         latencies {rid: seconds}, stats)."""
         pending = collections.deque(sorted(requests, key=lambda r: r.t_arrival))
-        waiting = collections.deque()
+        for r in pending:
+            if not (1 <= r.K <= self.k_max and 1 <= r.nprobe <= self.nprobe_max):
+                raise ValueError(f"request {r.rid}: K and nprobe must be in [1, k_max] and [1, nprobe_max]")
+        waiting = collections.OrderedDict()     # K class -> deque of requests
         inflight = []
         free_streams = list(self.streams)
         results, lat = {}, {}
@@ -130,7 +147,8 @@ class Server:
         while pending or waiting or inflight:
             now = time.perf_counter() - t0
             while pending and (not realtime or pending[0].t_arrival <= now):
-                waiting.append(pending.popleft())
+                r = pending.popleft()
+                waiting.setdefault(self.k_class(r.K), collections.deque()).append(r)
             done = [b for b in inflight if b.event.query()]
             if done:
                 t_done = time.perf_counter() - t0
@@ -142,10 +160,15 @@ class Server:
                         results[r.rid] = (b.h_ids[i, :k].numpy().copy(), b.h_dist[i, :k].numpy().copy())
                         lat[r.rid] = t_done - r.t_arrival if realtime else t_done
             if waiting and free_streams:
-                n = self.admission.admit(len(waiting), len(inflight),
-                                         sum(b.nbytes for b in inflight), self.batch_bytes)
+                cls = min(waiting, key=lambda c: waiting[c][0].t_arrival)
+                queue = waiting[cls]
+                k_cls = min(cls, self.k_max)
+                n = self.admission.admit(len(queue), len(inflight), sum(b.nbytes for b in inflight),
+                                         lambda m: self.batch_bytes(m, k_cls))
                 if n > 0:
-                    reqs = [waiting.popleft() for _ in range(n)]
+                    reqs = [queue.popleft() for _ in range(n)]
+                    if not queue:
+                        del waiting[cls]
                     inflight.append(self._launch(reqs, free_streams.pop()))
                     batches += 1
                     continue

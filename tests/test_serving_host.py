@@ -33,3 +33,8 @@ def test_stream_slots_and_empty_queue():
 def test_rejects_bad_configuration():
     with pytest.raises(ValueError):
         AdmissionController(0)
+
+
+def test_k_classes_are_powers_of_two():
+    from paper_2303_09855_amd.serving import Server
+    assert [Server.k_class(k) for k in (1, 2, 3, 10, 16, 17, 100)] == [1, 2, 4, 16, 16, 32, 128]
