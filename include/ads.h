@@ -259,7 +259,7 @@ ads_status ads_search(const ads_index *ix, const float *q, int32_t nq, const int
 
 /* ads_search_workspace_size -- HOST: bytes of workspace ads_search needs for
  * these sizes under the calling thread's queries_per_unit setting, for any
- * method, eps0 and dense_mfma (0 on invalid arguments, with ads_last_error set). */
+ * method, eps0 and dense_form (0 on invalid arguments, with ads_last_error set). */
 uint64_t ads_search_workspace_size(const ads_index *ix, int32_t nq, int32_t k_max,
                                    int32_t nprobe_max, int32_t rerank);
 
@@ -302,18 +302,18 @@ typedef struct {
                                  phase once at most this fraction of its (vector, query)
                                  pairs is alive.  Default 0.125. */
     int32_t queries_per_unit; /* 1, 2, 4, 8 or 16 queries per work unit; 0 = the largest
-                                 power of two up to 8 (16 with dense_mfma) whose KNN sets fit
+                                 power of two up to 8 (16 with dense_form 1) whose KNN sets fit
                                  in 4 KB of LDS.  Default 0. */
     int32_t sweep_log2;       /* probe ranks are scanned in sweeps [0,1), [1,g), [g,g^2), ...
                                  with g = 2^sweep_log2, sweep_log2 in [1, 6].  Default 4. */
     int32_t grid_per_xcd;     /* persistent scan workgroups per XCD, 0 = as many as the
                                  sweep has units (capped at 4096).  Default 0. */
-    int32_t dense_mfma;       /* 1: ADSampling / PDScanning scans evaluate the dense phase in
-                                 the dot-product form on the matrix cores and re-run, in the
-                                 canonical form, every pair whose decision the rounding
-                                 bound cannot settle (same results as 0); 0: register-dense
-                                 phase in the canonical form.  FDScanning always uses 0.
-                                 Default 0. */
+    int32_t dense_form;       /* dense phase of ADSampling / PDScanning scans: 0 = register
+                                 tiles, canonical form (subtract, square, add); 1 = dot-product
+                                 form on the matrix cores, which decides only where a
+                                 worst-case rounding bound settles the decision and re-runs
+                                 every other pair in the canonical form (same results as 0).
+                                 FDScanning always uses 0.  Default 0. */
 } ads_tuning;
 
 /* ads_set_tuning / ads_get_tuning -- HOST, per thread: knobs for later

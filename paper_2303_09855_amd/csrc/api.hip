@@ -181,22 +181,30 @@ struct SearchLayout {
     size_t off_qrot, off_qunit, off_qbn, off_dots, off_probes, off_kq, off_keff, off_npq, off_r2, off_tk, off_cnt,
         off_beg, off_cursor, off_uoff, off_xoff, off_xcnt, off_units, off_qent, off_slots, total;
     int nsweep, kcap, qw, lg;
-    bool mfma;
+    bool mfma, qnorms;               // matrix-core scan; query block norms needed
     int64_t ucap;
 };
 
 // The matrix-core scan serves the methods with finite test coefficients.
+// dense_form 1 (matrix cores) serves the methods with finite test
+// coefficients; FDScanning keeps the canonical form.
+int dense_form_for(float eps0, int method) {
+    if (g_tune.dense_form == 0 || method == ADS_METHOD_FDSCANNING) return 0;
+    if (method == ADS_METHOD_ADSAMPLING && std::isinf(eps0)) return 0;
+    return g_tune.dense_form;
+}
 bool use_mfma(float eps0, int method) {
-    if (!g_tune.dense_mfma || method == ADS_METHOD_FDSCANNING) return false;
+    if (g_tune.dense_form != 1 || method == ADS_METHOD_FDSCANNING) return false;
     return !(method == ADS_METHOD_ADSAMPLING && std::isinf(eps0));
 }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-SearchLayout layout_for(const ads_index *ix, int nq, int k_max, int nprobe_max, int rerank, bool mfma) {
+SearchLayout layout_for(const ads_index *ix, int nq, int k_max, int nprobe_max, int rerank, bool mfma, bool qnorms) {
     SearchLayout L{};
     L.kcap = k_max * (rerank ? 4 : 1);
     L.mfma = mfma;
+    L.qnorms = qnorms;
     L.qw = qw_for(L.kcap, mfma);
     L.lg = g_tune.sweep_log2;
     L.nsweep = num_sweeps(nprobe_max, L.lg);
@@ -205,7 +213,7 @@ SearchLayout layout_for(const ads_index *ix, int nq, int k_max, int nprobe_max, 
     const size_t nqs = (size_t)(nq > 0 ? nq : 1);
     L.off_qrot = take(nqs * ix->D * sizeof(float));
     L.off_qunit = take(ix->metric == ADS_METRIC_COSINE ? nqs * ix->D * sizeof(float) : 0);
-    L.off_qbn = take(mfma ? nqs * (ix->nb + 1) * sizeof(float) : 0);
+    L.off_qbn = take(qnorms ? nqs * (ix->nb + 1) * sizeof(float) : 0);
     L.off_dots = take(nqs * ix->nlist * sizeof(float));
     L.off_probes = take(nqs * nprobe_max * sizeof(int32_t));
     L.off_kq = take(nqs * sizeof(int32_t));
@@ -586,9 +594,12 @@ extern "C" uint64_t ads_search_workspace_size(const ads_index *ix, int32_t nq, i
                                               int32_t nprobe_max, int32_t rerank) {
     if (check_search_args(ix, nq, k_max, nprobe_max, rerank) != ADS_OK) return 0;
     // large enough for either scan variant (the method and eps0 pick one)
-    const size_t a = layout_for(ix, nq, k_max, nprobe_max, rerank, false).total;
-    const size_t b = layout_for(ix, nq, k_max, nprobe_max, rerank, true).total;
-    return (uint64_t)(a > b ? a : b);
+    size_t best = 0;
+    for (int f = 0; f < 2; ++f) {
+        const size_t t = layout_for(ix, nq, k_max, nprobe_max, rerank, f == 1, f != 0).total;
+        if (t > best) best = t;
+    }
+    return (uint64_t)best;
 }
 
 extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq, const int32_t *K,
@@ -606,7 +617,8 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
     HIP_TRY(hipGetLastError(), "pending HIP error");
 
     const int eff_method = std::isinf(eps0) && method == ADS_METHOD_ADSAMPLING ? ADS_METHOD_FDSCANNING : method;
-    const SearchLayout L = layout_for(ix, nq, k_max, nprobe_max, rerank, use_mfma(eps0, eff_method));
+    const int form = dense_form_for(eps0, eff_method);
+    const SearchLayout L = layout_for(ix, nq, k_max, nprobe_max, rerank, form == 1, form != 0);
     const int qw = L.qw;
     const int D = ix->D, nlist = ix->nlist;
     unsigned char *ws = reinterpret_cast<unsigned char *>(workspace);
@@ -666,7 +678,7 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
             qsrc = qunit;
         }
         SEARCH_TRY(gemm_nt_f32(qsrc, D, ix->P, D, qrot, D, nq, D, D, stream), "rotate queries");
-        if (L.mfma)
+        if (L.qnorms)
             SEARCH_TRY(launch_query_block_norms(qrot, nq, D, ix->dd, reinterpret_cast<float *>(ws + L.off_qbn), stream),
                        "query block norms");
     }
@@ -840,8 +852,8 @@ extern "C" ads_status ads_set_tuning(const ads_tuning *t) {
         return fail(ADS_EINVAL, "sweep_log2 must be in [1, 6] (got %d)", t->sweep_log2);
     if (t->grid_per_xcd < 0 || t->grid_per_xcd > 65536)
         return fail(ADS_EINVAL, "grid_per_xcd must be in [0, 65536] (got %d)", t->grid_per_xcd);
-    if (t->dense_mfma != 0 && t->dense_mfma != 1)
-        return fail(ADS_EINVAL, "dense_mfma must be 0 or 1 (got %d)", t->dense_mfma);
+    if (t->dense_form != 0 && t->dense_form != 1)
+        return fail(ADS_EINVAL, "dense_form must be 0 or 1 (got %d)", t->dense_form);
     g_tune = *t;
     return ADS_OK;
 }

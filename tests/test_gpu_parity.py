@@ -278,31 +278,33 @@ _MC_CASES = [
 
 
 @pytest.mark.parametrize("fixture,dd,storage,method,eps0,K,nprobe,qpu", _MC_CASES)
-def test_matrix_core_scan_equals_register_scan(ads, request, fixture, dd, storage, method, eps0, K,
-                                               nprobe, qpu):
-    """The matrix-core dense phase (dot-product form) acts only on decisions
-    its rounding bound settles and sends every other pair through the
-    canonical form, so ids, distances and every statistic (DCOs, sampled
-    dimensions, positives) equal those of the register-dense scan bit for bit.
-    The mixture data of ivf128 sits far from the origin (norms ~20x the
-    distances), which puts many tests inside the rounding band."""
+def test_dense_forms_give_identical_results(ads, request, fixture, dd, storage, method, eps0, K,
+                                            nprobe, qpu):
+    """The dot-product dense phase on the matrix cores (form 1) acts only on
+    decisions its rounding bound settles and sends every other pair through
+    the canonical form, so ids, distances and every statistic (DCOs, sampled
+    dimensions, positives) equal those of the canonical register scan
+    (form 0) bit for bit.  The mixture data of ivf128
+    sits far from the origin (norms ~20x the distances), which puts many
+    tests inside the rounding band."""
     w, _ = request.getfixturevalue(fixture)
     ix = _build(ads, w, dd=dd, storage=storage)
     saved = ads.get_tuning()
     res = {}
     try:
-        for mf in (0, 1):
-            ads.set_tuning(dense_mfma=mf, queries_per_unit=qpu)
+        for form in (0, 1):
+            ads.set_tuning(dense_form=form, queries_per_unit=qpu)
             stats = torch.zeros(ads.NSTATS, dtype=torch.int64, device="cuda")
             ids, dist = ads.search(ix, w.q, K, nprobe, eps0=eps0, method=method, stats=stats)
-            res[mf] = (_np(ids), _np(dist), _np(stats))
+            res[form] = (_np(ids), _np(dist), _np(stats))
     finally:
         ads.set_tuning(**saved)
         ix.free()
-    assert np.array_equal(res[0][0], res[1][0])
-    assert np.array_equal(res[0][1], res[1][1])
-    assert np.array_equal(res[0][2], res[1][2]), (res[0][2], res[1][2])
-    assert res[1][2][ads.STAT_DIMS] < res[1][2][ads.STAT_DCOS] * w.D
+    for form in (1,):
+        assert np.array_equal(res[0][0], res[form][0]), form
+        assert np.array_equal(res[0][1], res[form][1]), form
+        assert np.array_equal(res[0][2], res[form][2]), (form, res[0][2], res[form][2])
+    assert res[0][2][ads.STAT_DIMS] < res[0][2][ads.STAT_DCOS] * w.D
 
 
 # ---------------------------------------------------------------------------
