@@ -492,13 +492,46 @@ __device__ inline int xcd_major_list(int i, int nlist) {
     return -1;
 }
 
+// Order of the lists of one XCD in one sweep (workgroup (sweep, xcd)):
+// decreasing work (queries x list length), ties by list id, so the longest
+// units start first and do not form the tail of the launch.  The order
+// changes no result.  order[s * nlist + i] is the list at XCD-major
+// position i (XCD x holds positions of lists x, x + 8, ...).
+constexpr int ORDER_MAX = 4096;     // lists per XCD sorted in LDS
+
+__global__ __launch_bounds__(512) void list_order_kernel(const int32_t *cnt, const int64_t *list_off, int nlist,
+                                                         int32_t *order) {
+    __shared__ uint64_t key[ORDER_MAX];
+    const int s = blockIdx.x >> 3, x = blockIdx.x & 7;
+    const int nx = x < nlist ? (nlist - x + 7) / 8 : 0;
+    int start = 0;
+    for (int y = 0; y < x; ++y) start += y < nlist ? (nlist - y + 7) / 8 : 0;
+    const int np2 = next_pow2(nx > 0 ? nx : 1);
+    const uint64_t cap = (1ull << 40) - 1;
+    for (int j = threadIdx.x; j < np2; j += blockDim.x) {
+        uint64_t k = ~0ull;
+        if (j < nx) {
+            const int l = x + 8 * j;
+            uint64_t work = (uint64_t)cnt[(int64_t)s * nlist + l] * (uint64_t)(list_off[l + 1] - list_off[l]);
+            work = work > cap ? cap : work;
+            k = ((cap - work) << 24) | (uint64_t)j;
+        }
+        key[j] = k;
+    }
+    __syncthreads();
+    lds_bitonic_sort(key, np2);
+    for (int j = threadIdx.x; j < nx; j += blockDim.x)
+        order[(int64_t)s * nlist + start + j] = x + 8 * (int)(key[j] & 0xffffffu);
+}
+
 // One workgroup of 1024 threads.  Per sweep: exclusive prefix of cnt over
 // lists (entry offsets into qent, continuing across sweeps) and the unit
 // offsets of every list in XCD-major order (ceil(cnt / qw) units per list),
-// with the first unit and the unit count of every XCD.
-__global__ __launch_bounds__(1024) void group_scan_kernel(const int32_t *cnt, int nsweep, int nlist, int qw,
-                                                          int32_t *beg, int32_t *uoff, int32_t *xoff,
-                                                          int32_t *xcnt) {
+// with the first unit and the unit count of every XCD.  order (or NULL for
+// ascending list id within an XCD) gives the lists' order inside each XCD.
+__global__ __launch_bounds__(1024) void group_scan_kernel(const int32_t *cnt, const int32_t *order, int nsweep,
+                                                          int nlist, int qw, int32_t *beg, int32_t *uoff,
+                                                          int32_t *xoff, int32_t *xcnt) {
     __shared__ int32_t sa[1024];
     __shared__ int32_t carry;
     __shared__ int32_t xfirst[9];
@@ -529,7 +562,7 @@ __global__ __launch_bounds__(1024) void group_scan_kernel(const int32_t *cnt, in
         __syncthreads();
         for (int i0 = 0; i0 < nlist; i0 += 1024) {
             const int i = i0 + threadIdx.x;
-            const int l = i < nlist ? xcd_major_list(i, nlist) : -1;
+            const int l = i < nlist ? (order ? order[(int64_t)s * nlist + i] : xcd_major_list(i, nlist)) : -1;
             const int c = l >= 0 ? cnt[(int64_t)s * nlist + l] : 0;
             const int ng = (c + qw - 1) / qw;
             sa[threadIdx.x] = ng;
@@ -544,7 +577,9 @@ __global__ __launch_bounds__(1024) void group_scan_kernel(const int32_t *cnt, in
             if (l >= 0) {
                 uoff[(int64_t)s * nlist + l] = ex;
                 const int xl = l & 7;
-                if (l == xl) xfirst[xl] = ex;   // the first list of block xl
+                // the first list of XCD xl's range
+                const bool first = order ? (i == 0 || (order[(int64_t)s * nlist + i - 1] & 7) != xl) : l == xl;
+                if (first) xfirst[xl] = ex;
             }
             __syncthreads();
             if (threadIdx.x == 1023) ucarry += sa[1023];
