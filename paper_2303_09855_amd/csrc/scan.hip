@@ -632,6 +632,8 @@ __global__ void group_scatter_kernel(const int32_t *probes, const int32_t *npq, 
 // Merge after a sweep: the KNN set of query q becomes the keff[q] smallest
 // keys among its previous set and the sweep's per-list sets.
 // ---------------------------------------------------------------------------
+constexpr int MERGE_LDS = 2048;   // keys a merge sorts in LDS
+
 __global__ __launch_bounds__(ADS_WG) void merge_kernel(const uint64_t *slots, const int32_t *keff,
                                                       const int32_t *npq, int nprobe_max, int kcap,
                                                       int rank_a, int rank_b, uint64_t *tk,
@@ -648,13 +650,30 @@ __global__ __launch_bounds__(ADS_WG) void merge_kernel(const uint64_t *slots, co
     const uint64_t *ms = slots + ((int64_t)q * nprobe_max + rank_a) * kcap;
     const int n = kcap + (hi - rank_a) * kcap;
     auto get = [&](int i) -> uint64_t { return i < kcap ? mytk[i] : ms[i - kcap]; };
+    // Most slots are empty (a unit publishes only its positives): gather the
+    // keys that are present into LDS in one pass and sort them there; fall
+    // back to a radix select over the slots when they do not fit.
+    __shared__ uint64_t cmp[MERGE_LDS];
     if (threadIdx.x == 0) misc[3] = 0;
     __syncthreads();
-    uint32_t nv_local = 0;
-    for (int i = threadIdx.x; i < n; i += ADS_WG) nv_local += get(i) != KEY_NONE;
-    if (nv_local) atomicAdd(&misc[3], nv_local);
+    for (int i = threadIdx.x; i < n; i += ADS_WG) {
+        const uint64_t key = get(i);
+        if (key != KEY_NONE) {
+            const uint32_t p = atomicAdd(&misc[3], 1u);
+            if (p < (uint32_t)MERGE_LDS) cmp[p] = key;
+        }
+    }
     __syncthreads();
     const int nv = (int)misc[3];
+    if (nv <= MERGE_LDS) {
+        const int P2 = next_pow2(nv > 0 ? nv : 1);
+        for (int i = nv + threadIdx.x; i < P2; i += ADS_WG) cmp[i] = KEY_NONE;
+        __syncthreads();
+        lds_bitonic_sort(cmp, P2);
+        for (int i = threadIdx.x; i < kcap; i += ADS_WG) mytk[i] = i < K && i < nv ? cmp[i] : KEY_NONE;
+        if (threadIdx.x == 0) r2[q] = nv >= K ? key_dist2(cmp[K - 1]) : __builtin_inff();
+        return;
+    }
     uint64_t kth = KEY_NONE;
     if (nv > K) kth = radix_kth(get, n, K, hist, misc);
     const int P = next_pow2(kcap);
