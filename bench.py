@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--target-recall", type=float, default=0.95)
     ap.add_argument("--K", type=int, default=10)
     ap.add_argument("--eps0", type=float, default=2.1)
-    ap.add_argument("--delta-d", type=int, default=32)
+    ap.add_argument("--delta-d", type=int, default=16)
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample")

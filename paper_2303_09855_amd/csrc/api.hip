@@ -62,7 +62,7 @@ struct ads_index {
 namespace {
 
 thread_local std::string g_err;
-thread_local ads_tuning g_tune = {0.125f, 0, 4, 0, 0};
+thread_local ads_tuning g_tune = {0.f, 0, 4, 0, 0};
 
 // Per-thread event profiler (ads_profile_enable / ads_profile_collect).
 struct Profiler {
@@ -738,7 +738,9 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
         a.kcap = L.kcap;
         a.D = D;
         a.nb = ix->nb;
-        a.dense_frac = g_tune.dense_frac;
+        // automatic: smaller blocks make the register-dense phase cheaper per
+        // test, so it is kept longer (measured best on the D = 960 workload)
+        a.dense_frac = g_tune.dense_frac > 0.f ? g_tune.dense_frac : (ix->dd <= 16 ? 0.25f : 0.125f);
         a.round_tiles = s < WIDE_SWEEPS ? 4 : 1;
         a.blk_norm = ix->blk_norm;
         a.vec_norm = ix->vec_norm;
@@ -853,8 +855,8 @@ extern "C" ads_status ads_plan_free(ads_plan *plan) {
 
 extern "C" ads_status ads_set_tuning(const ads_tuning *t) {
     if (!t) return fail(ADS_EINVAL, "tuning must not be NULL");
-    if (!(t->dense_frac > 0.f && t->dense_frac <= 0.25f))
-        return fail(ADS_EINVAL, "dense_frac must be in (0, 0.25] (got %g)", (double)t->dense_frac);
+    if (!(t->dense_frac == 0.f || (t->dense_frac > 0.f && t->dense_frac <= 0.25f)))
+        return fail(ADS_EINVAL, "dense_frac must be 0 (automatic) or in (0, 0.25] (got %g)", (double)t->dense_frac);
     if (t->queries_per_unit != 0 && t->queries_per_unit != 1 && t->queries_per_unit != 2 &&
         t->queries_per_unit != 4 && t->queries_per_unit != 8 && t->queries_per_unit != 16)
         return fail(ADS_EINVAL, "queries_per_unit must be 0, 1, 2, 4, 8 or 16 (got %d)", t->queries_per_unit);
