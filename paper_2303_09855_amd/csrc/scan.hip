@@ -36,14 +36,15 @@ namespace ads {
 
 // W waves per workgroup: each takes one 64-vector tile per round, and the
 // round's positives lower the thresholds before the next round.
-template <int DD, int QW, int W>
+template <int DD, int QW, int W, int NQB>
 struct ScanSmem {
     static constexpr int LCAP = 16 * QW;   // pairs alive when the dense phase hands over (<= 1/4)
     // wave-private
-    float qs[W][2][QW][DD + 4];     // query block, double-buffered
+    float qs[W][NQB][QW][DD + 4];   // query block (double-buffered when prefetching)
     uint64_t list[W][2][LCAP];
     uint64_t pos[W][QW][64];
     int pcnt[W][QW];
+    float thr[W][QW];               // rejection thresholds of the current block
     // shared by the unit
     float r2s[QW];
     int qidx[QW], qrank[QW], qk[QW], tkcnt[QW], tkmax[QW];
@@ -55,10 +56,10 @@ struct ScanSmem {
 template <int DT, int DD, int QW, bool PF, int W>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(PF ? 2 : 4))) void scan_kernel(ScanArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    ScanSmem<DD, QW, W> &sm = *reinterpret_cast<ScanSmem<DD, QW, W> *>(smem_raw);
-    float *coef = reinterpret_cast<float *>(smem_raw + sizeof(ScanSmem<DD, QW, W>));
-    uint64_t *tk = reinterpret_cast<uint64_t *>(
-        smem_raw + ((sizeof(ScanSmem<DD, QW, W>) + sizeof(float) * a.nb + 15) & ~(size_t)15));
+    using Smem = ScanSmem<DD, QW, W, PF ? 2 : 1>;
+    Smem &sm = *reinterpret_cast<Smem *>(smem_raw);
+    float *coef = reinterpret_cast<float *>(smem_raw + sizeof(Smem));
+    uint64_t *tk = reinterpret_cast<uint64_t *>(smem_raw + ((sizeof(Smem) + sizeof(float) * a.nb + 15) & ~(size_t)15));
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int x = blockIdx.x & 7;
@@ -110,16 +111,24 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(PF ? 2 :
             if (lane < QW) pcnt[lane] = 0;
             const int v = vc + lane;
             const bool vvalid = v < nl;
+            // am[jj]: lanes whose pair (the lane's vector, query jj) is
+            // undecided, as a wave-uniform lane mask, so that liveness tests and
+            // updates are scalar operations
             float S[QW];
-            uint32_t alive = 0;
+            uint64_t am[QW];
+            uint64_t amany = 0;
+            int tile_pairs = 0;
 #pragma unroll
             for (int jj = 0; jj < QW; ++jj) {
                 S[jj] = 0.f;
-                if (vvalid && jj < qc && sm.qk[jj] > 0) alive |= 1u << jj;
+                am[jj] = __ballot(vvalid && jj < qc && sm.qk[jj] > 0);
+                amany |= am[jj];
+                tile_pairs += __popcll(am[jj]);
             }
-            int tile_pairs = 0;
-#pragma unroll
-            for (int jj = 0; jj < QW; ++jj) tile_pairs += __popcll(__ballot((alive >> jj) & 1u));
+            // sampled dimensions of the pairs decided in the dense phase,
+            // counted per wave: each pair decided in block b samples (b+1) DD
+            unsigned long long wdims = 0;
+            int na_prev = tile_pairs;
             int b = 0, m = 0;
             bool sparse = false;
             wave_sync();
@@ -150,7 +159,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(PF ? 2 :
             if (PF && tile_pairs > 0) {
                 float4 qv[QPL];
                 fetch_q(0, qv);
-                if (alive) load_elems<DT, DD>(lbase + ((int64_t)v * DD) * EB, o);
+                if ((amany >> lane) & 1ull) load_elems<DT, DD>(lbase + ((int64_t)v * DD) * EB, o);
                 store_q(qv, sm.qs[w][0]);
             }
             for (; tile_pairs > 0 && b < nb; ++b) {
@@ -159,43 +168,49 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(PF ? 2 :
                 if constexpr (PF) {
                     const int bn = b + 1 < nb ? b + 1 : b;
                     fetch_q(bn, qv1);
-                    if (alive) load_elems<DT, DD>(lbase + ((int64_t)bn * nl * DD + (int64_t)v * DD) * EB, o1);
+                    if ((amany >> lane) & 1ull) load_elems<DT, DD>(lbase + ((int64_t)bn * nl * DD + (int64_t)v * DD) * EB, o1);
                 } else {
-                    if (alive) load_elems<DT, DD>(lbase + ((int64_t)b * nl * DD + (int64_t)v * DD) * EB, o);
+                    if ((amany >> lane) & 1ull) load_elems<DT, DD>(lbase + ((int64_t)b * nl * DD + (int64_t)v * DD) * EB, o);
                     fetch_q(b, qv1);
                     store_q(qv1, sm.qs[w][0]);
                 }
                 float(*qs)[DD + 4] = sm.qs[w][qb];
-                wave_sync();
                 const int d = (b + 1) * DD;
-                const float cf = coef[b];
-                if (alive) {
+                // rejection thresholds of the block: S > coef(d) r^2 (an infinite
+                // coefficient gives +inf or NaN, and neither rejects)
+                if (lane < QW) sm.thr[w][lane] = coef[b] * sm.r2s[lane];
+                wave_sync();
+                // canonical order: the block's partial from zero, then S += partial.
+                // A query with no undecided pair in the tile is skipped by the
+                // whole wave; lanes of decided pairs compute along, without effect.
+                auto advance = [&](int jj) {
+                    float pb = 0.f;
+#pragma unroll
+                    for (int kk = 0; kk < DD; ++kk) {
+                        float df = o[kk] - qs[jj][kk];
+                        pb = __fmaf_rn(df, df, pb);
+                    }
+                    return S[jj] + pb;
+                };
+                if (d < D) {
 #pragma unroll
                     for (int jj = 0; jj < QW; ++jj) {
-                        if (!((alive >> jj) & 1u)) continue;
-                        // canonical order: the block's partial from zero, then S += partial
-                        float pb = 0.f;
-#pragma unroll
-                        for (int kk = 0; kk < DD; ++kk) {
-                            float df = o[kk] - qs[jj][kk];
-                            pb = __fmaf_rn(df, df, pb);
-                        }
-                        const float s = S[jj] + pb;
+                        if (am[jj] == 0) continue;
+                        const float s = advance(jj);
                         S[jj] = s;
-                        if (d < D) {
-                            if (test_reject(s, cf, sm.r2s[jj])) {
-                                alive &= ~(1u << jj);
-                                my_dims += d;
-                            }
-                        } else {
-                            alive &= ~(1u << jj);
-                            my_dims += D;
-                            if (s <= sm.r2s[jj]) {
-                                const int p = atomicAdd(&pcnt[jj], 1);
-                                sm.pos[w][jj][p] = make_key(s, (uint32_t)a.ids[off + v]);
-                                ++my_pos;
-                            }
+                        am[jj] &= ~__ballot(s > sm.thr[w][jj]);
+                    }
+                } else {
+#pragma unroll
+                    for (int jj = 0; jj < QW; ++jj) {
+                        if (am[jj] == 0) continue;
+                        const float s = advance(jj);
+                        if (((am[jj] >> lane) & 1ull) && s <= sm.r2s[jj]) {
+                            const int p = atomicAdd(&pcnt[jj], 1);
+                            sm.pos[w][jj][p] = make_key(s, (uint32_t)a.ids[off + v]);
+                            ++my_pos;
                         }
+                        am[jj] = 0;
                     }
                 }
                 if constexpr (PF) {
@@ -205,17 +220,26 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(PF ? 2 :
                     for (int k = 0; k < DD; ++k) o[k] = o1[k];
                 }
                 wave_sync();
-                if (d >= D) break;
+                if (d >= D) {
+                    wdims += (unsigned long long)na_prev * (unsigned long long)D;
+                    break;
+                }
                 int na = 0;
+                amany = 0;
 #pragma unroll
-                for (int jj = 0; jj < QW; ++jj) na += __popcll(__ballot((alive >> jj) & 1u));
+                for (int jj = 0; jj < QW; ++jj) {
+                    na += __popcll(am[jj]);
+                    amany |= am[jj];
+                }
+                wdims += (unsigned long long)(na_prev - na) * (unsigned long long)d;
+                na_prev = na;
                 if (na == 0) break;
                 if ((float)na <= a.dense_frac * (float)tile_pairs) {
                     uint64_t *list = sm.list[w][0];
                     int base = 0;
 #pragma unroll
                     for (int jj = 0; jj < QW; ++jj) {
-                        const bool bit = (alive >> jj) & 1u;
+                        const bool bit = (am[jj] >> lane) & 1ull;
                         const uint64_t msk = __ballot(bit);
                         if (bit) {
                             const int p = base + __popcll(msk & lanemask_lt);
@@ -229,6 +253,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(PF ? 2 :
                     break;
                 }
             }
+            if (lane == 0) my_dims += wdims;
             // the surviving pairs run to their decisions in the pair-list phase
             if (sparse) {
                 SparseCtx ctx;
@@ -310,9 +335,9 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(PF ? 2 :
     }
 }
 
-template <int DD, int QW, int W>
+template <int DD, int QW, int W, bool PF>
 size_t scan_smem_bytes(int nb, int kcap) {
-    size_t s = sizeof(ScanSmem<DD, QW, W>) + sizeof(float) * nb;
+    size_t s = sizeof(ScanSmem<DD, QW, W, PF ? 2 : 1>) + sizeof(float) * nb;
     s = (s + 15) & ~(size_t)15;
     return s + sizeof(uint64_t) * (size_t)QW * kcap;
 }
@@ -324,13 +349,13 @@ hipError_t launch_scan_t(const ScanArgs &a, int grid, bool pf, bool wide, hipStr
     // rounds of four tiles on four waves when the LDS fits, else on one wave
     // (same thresholds, same results)
     if (wide && a.round_tiles == 4) {
-        const size_t sh = scan_smem_bytes<DD, QW, 4>(a.nb, a.kcap);
+        const size_t sh = scan_smem_bytes<DD, QW, 4, false>(a.nb, a.kcap);
         if (sh <= 64 * 1024) {
             hipLaunchKernelGGL((scan_kernel<DT, DD, QW, false, 4>), dim3(grid), dim3(256), sh, s, a);
             return hipGetLastError();
         }
     }
-    const size_t sh = scan_smem_bytes<DD, QW, 1>(a.nb, a.kcap);
+    const size_t sh = pf ? scan_smem_bytes<DD, QW, 1, true>(a.nb, a.kcap) : scan_smem_bytes<DD, QW, 1, false>(a.nb, a.kcap);
     if (sh > 64 * 1024) return hipErrorInvalidValue;
     if (pf)
         hipLaunchKernelGGL((scan_kernel<DT, DD, QW, true, 1>), dim3(grid), dim3(64), sh, s, a);
