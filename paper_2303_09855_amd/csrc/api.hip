@@ -18,10 +18,10 @@ __global__ void probe_select_kernel(const float *qrot, const float *dots, const 
                                     int nlist, int nprobe_max, int32_t *probes);
 __global__ void group_count_kernel(const int32_t *probes, const int32_t *npq, const int32_t *keff,
                                    int nq, int nprobe_max, int nlist, int lg, int32_t *cnt);
-__global__ void list_order_kernel(const int32_t *cnt, const int64_t *list_off, int nlist, int32_t *order);
-__global__ void group_scan_kernel(const int32_t *cnt, const int32_t *order, int nsweep, int nlist, int qw,
-                                  int32_t *beg,
-                                  int32_t *uoff, int32_t *xoff, int32_t *xcnt);
+__global__ void list_order_kernel(const int32_t *cnt, const int64_t *list_off, int nlist, int32_t *order,
+                                  int32_t *xb);
+__global__ void group_scan_kernel(const int32_t *cnt, const int32_t *order, const int32_t *xb, int nsweep,
+                                  int nlist, int qw, int32_t *beg, int32_t *uoff, int32_t *xoff, int32_t *xcnt);
 __global__ void unit_expand_kernel(const int32_t *cnt, const int32_t *beg, const int32_t *uoff, int nsweep,
                                    int nlist, int qw, int64_t ucap, int4 *units);
 __global__ void group_scatter_kernel(const int32_t *probes, const int32_t *npq, const int32_t *keff,
@@ -180,7 +180,7 @@ constexpr int WIDE_SWEEPS = ADS_WIDE_SWEEPS;
 constexpr int NPROBE_MAX_LIMIT = 8192;
 
 struct SearchLayout {
-    size_t off_qrot, off_qunit, off_qbn, off_order, off_dots, off_probes, off_kq, off_keff, off_npq, off_r2, off_tk, off_cnt,
+    size_t off_qrot, off_qunit, off_qbn, off_order, off_xb, off_dots, off_probes, off_kq, off_keff, off_npq, off_r2, off_tk, off_cnt,
         off_beg, off_cursor, off_uoff, off_xoff, off_xcnt, off_units, off_qent, off_slots, total;
     int nsweep, kcap, qw, lg;
     bool mfma, qnorms;               // matrix-core scan; query block norms needed
@@ -229,6 +229,7 @@ SearchLayout layout_for(const ads_index *ix, int nq, int k_max, int nprobe_max, 
     L.off_beg = take(sl * sizeof(int32_t));
     L.off_uoff = take(sl * sizeof(int32_t));
     L.off_order = take(sl * sizeof(int32_t));
+    L.off_xb = take((size_t)L.nsweep * 9 * sizeof(int32_t));
     L.off_xoff = take((size_t)L.nsweep * 8 * sizeof(int32_t));
     L.off_xcnt = take((size_t)L.nsweep * 8 * sizeof(int32_t));
     L.ucap = ((int64_t)nqs * nprobe_max + L.qw - 1) / L.qw + ix->nlist;
@@ -699,15 +700,12 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
         PhaseTimer t(ADS_PHASE_GROUP, stream);
         hipLaunchKernelGGL(group_count_kernel, dim3(grid_for((int64_t)nq * nprobe_max)), dim3(ADS_WG), 0, stream,
                            probes, npq, keff, nq, nprobe_max, nlist, L.lg, cnt);
-        int32_t *order = nullptr;
-        if ((nlist + 7) / 8 <= 4096) {
-            order = reinterpret_cast<int32_t *>(ws + L.off_order);
-            hipLaunchKernelGGL(list_order_kernel, dim3(8 * L.nsweep), dim3(512), 0, stream, cnt, ix->list_off, nlist,
-                               order);
-        }
-        hipLaunchKernelGGL(group_scan_kernel, dim3(1), dim3(1024), 0, stream, cnt, order, L.nsweep, nlist, qw,
-                           beg, uoff,
-                           xoff, xcnt);
+        int32_t *order = reinterpret_cast<int32_t *>(ws + L.off_order);
+        int32_t *xb = reinterpret_cast<int32_t *>(ws + L.off_xb);
+        hipLaunchKernelGGL(list_order_kernel, dim3(8 * L.nsweep), dim3(512), 0, stream, cnt, ix->list_off, nlist,
+                           order, xb);
+        hipLaunchKernelGGL(group_scan_kernel, dim3(1), dim3(1024), 0, stream, cnt, order, xb, L.nsweep, nlist, qw,
+                           beg, uoff, xoff, xcnt);
         hipLaunchKernelGGL(group_scatter_kernel, dim3(grid_for((int64_t)nq * nprobe_max)), dim3(ADS_WG), 0, stream,
                            probes, npq, keff, nq, nprobe_max, nlist, L.lg, beg, cursor, qent);
         hipLaunchKernelGGL(unit_expand_kernel, dim3(grid_for(sl)), dim3(ADS_WG), 0, stream, cnt, beg, uoff,

@@ -505,57 +505,101 @@ __global__ void group_count_kernel(const int32_t *probes, const int32_t *npq, co
     }
 }
 
-// Position i of the XCD-major order -> list id: lists x, x+8, x+16, ... form
-// block x of the order.
-__device__ inline int xcd_major_list(int i, int nlist) {
-    int start = 0;
-    for (int x = 0; x < 8; ++x) {
-        const int nx = x < nlist ? (nlist - x + 7) / 8 : 0;
-        if (i < start + nx) return x + 8 * (i - start);
-        start += nx;
-    }
-    return -1;
-}
-
-// Order of the lists of one XCD in one sweep (workgroup (sweep, xcd)):
-// decreasing work (queries x list length), ties by list id, so the longest
-// units start first and do not form the tail of the launch.  The order
-// changes no result.  order[s * nlist + i] is the list at XCD-major
-// position i (XCD x holds positions of lists x, x + 8, ...).
-constexpr int ORDER_MAX = 4096;     // lists per XCD sorted in LDS
+// Lists of one sweep -> XCDs.  The work of a list in a sweep is its query
+// count times its length; XCD x owns the contiguous range of list ids whose
+// work midpoints fall in the x-th eighth of the sweep's total work, so the
+// eight XCDs (each with its own L2) get equal shares whatever the list sizes
+// and query popularity.  Within its range an XCD takes the lists in
+// decreasing work (ties by list id), so the longest units start first and do
+// not form the tail of the launch.  Neither changes any result.
+// Workgroup (sweep s, XCD x) writes order[s * nlist + i] for the positions i
+// of its range and xb[s * 9 + x] = the range's first position (xb[s * 9 + 8]
+// = nlist).
+constexpr int ORDER_MAX = 4096;     // lists of one range sorted in LDS (larger ranges keep id order)
 
 __global__ __launch_bounds__(512) void list_order_kernel(const int32_t *cnt, const int64_t *list_off, int nlist,
-                                                         int32_t *order) {
+                                                         int32_t *order, int32_t *xb) {
     __shared__ uint64_t key[ORDER_MAX];
-    const int s = blockIdx.x >> 3, x = blockIdx.x & 7;
-    const int nx = x < nlist ? (nlist - x + 7) / 8 : 0;
-    int start = 0;
-    for (int y = 0; y < x; ++y) start += y < nlist ? (nlist - y + 7) / 8 : 0;
-    const int np2 = next_pow2(nx > 0 ? nx : 1);
+    __shared__ unsigned long long part[512];
+    __shared__ int cnt_lo[512], cnt_hi[512];
+    const int s = blockIdx.x >> 3, x = blockIdx.x & 7, t = threadIdx.x;
+    const int32_t *c = cnt + (int64_t)s * nlist;
+    auto work = [&](int l) -> unsigned long long {
+        return (unsigned long long)c[l] * (unsigned long long)(list_off[l + 1] - list_off[l]);
+    };
+    // each thread takes a contiguous chunk of list ids; exclusive prefix of the chunk sums
+    const int per = (nlist + 511) / 512;
+    const int l0 = min(nlist, t * per), l1 = min(nlist, l0 + per);
+    unsigned long long sum = 0;
+    for (int l = l0; l < l1; ++l) sum += work(l);
+    part[t] = sum;
+    __syncthreads();
+    for (int o = 1; o < 512; o <<= 1) {
+        const unsigned long long v = t >= o ? part[t - o] : 0ull;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    const unsigned long long total = part[511];
+    unsigned long long pre = part[t] - sum;
+    // XCD of every list; the ranges are counted, so they partition the ids
+    int lo = 0, hi = 0;
+    for (int l = l0; l < l1; ++l) {
+        const unsigned long long wl = work(l);
+        int xl;
+        if (total == 0) {
+            xl = (int)((int64_t)l * 8 / nlist);
+        } else {
+            xl = (int)(8.0 * ((double)pre + 0.5 * (double)wl) / (double)total);
+            xl = xl > 7 ? 7 : xl;
+        }
+        lo += xl < x;
+        hi += xl <= x;
+        pre += wl;
+    }
+    cnt_lo[t] = lo;
+    cnt_hi[t] = hi;
+    __syncthreads();
+    for (int o = 256; o > 0; o >>= 1) {
+        if (t < o) {
+            cnt_lo[t] += cnt_lo[t + o];
+            cnt_hi[t] += cnt_hi[t + o];
+        }
+        __syncthreads();
+    }
+    const int start = cnt_lo[0], n = cnt_hi[0] - cnt_lo[0];
+    if (t == 0) {
+        xb[s * 9 + x] = start;
+        if (x == 7) xb[s * 9 + 8] = nlist;
+    }
+    int32_t *ord = order + (int64_t)s * nlist + start;
+    if (n > ORDER_MAX) {
+        for (int j = t; j < n; j += blockDim.x) ord[j] = start + j;
+        return;
+    }
+    const int np2 = next_pow2(n > 0 ? n : 1);
     const uint64_t cap = (1ull << 40) - 1;
-    for (int j = threadIdx.x; j < np2; j += blockDim.x) {
+    for (int j = t; j < np2; j += blockDim.x) {
         uint64_t k = ~0ull;
-        if (j < nx) {
-            const int l = x + 8 * j;
-            uint64_t work = (uint64_t)cnt[(int64_t)s * nlist + l] * (uint64_t)(list_off[l + 1] - list_off[l]);
-            work = work > cap ? cap : work;
-            k = ((cap - work) << 24) | (uint64_t)j;
+        if (j < n) {
+            uint64_t wl = work(start + j);
+            wl = wl > cap ? cap : wl;
+            k = ((cap - wl) << 24) | (uint64_t)j;
         }
         key[j] = k;
     }
     __syncthreads();
     lds_bitonic_sort(key, np2);
-    for (int j = threadIdx.x; j < nx; j += blockDim.x)
-        order[(int64_t)s * nlist + start + j] = x + 8 * (int)(key[j] & 0xffffffu);
+    for (int j = t; j < n; j += blockDim.x) ord[j] = start + (int)(key[j] & 0xffffffu);
 }
 
 // One workgroup of 1024 threads.  Per sweep: exclusive prefix of cnt over
 // lists (entry offsets into qent, continuing across sweeps) and the unit
-// offsets of every list in XCD-major order (ceil(cnt / qw) units per list),
-// with the first unit and the unit count of every XCD.  order (or NULL for
-// ascending list id within an XCD) gives the lists' order inside each XCD.
-__global__ __launch_bounds__(1024) void group_scan_kernel(const int32_t *cnt, const int32_t *order, int nsweep,
-                                                          int nlist, int qw, int32_t *beg, int32_t *uoff,
+// offsets of every list in the XCD-major order of list_order_kernel
+// (ceil(cnt / qw) units per list), with the first unit and the unit count of
+// every XCD.
+__global__ __launch_bounds__(1024) void group_scan_kernel(const int32_t *cnt, const int32_t *order, const int32_t *xb,
+                                                          int nsweep, int nlist, int qw, int32_t *beg, int32_t *uoff,
                                                           int32_t *xoff, int32_t *xcnt) {
     __shared__ int32_t sa[1024];
     __shared__ int32_t carry;
@@ -580,14 +624,15 @@ __global__ __launch_bounds__(1024) void group_scan_kernel(const int32_t *cnt, co
             if (threadIdx.x == 1023) carry += sa[1023];
             __syncthreads();
         }
-        // unit offsets in XCD-major list order
+        // unit offsets in XCD-major order; xfirst[x] = first unit of XCD x
         __shared__ int32_t ucarry;
         if (threadIdx.x == 0) ucarry = 0;
         if (threadIdx.x < 9) xfirst[threadIdx.x] = -1;
         __syncthreads();
+        const int32_t *xbs = xb + s * 9;
         for (int i0 = 0; i0 < nlist; i0 += 1024) {
             const int i = i0 + threadIdx.x;
-            const int l = i < nlist ? (order ? order[(int64_t)s * nlist + i] : xcd_major_list(i, nlist)) : -1;
+            const int l = i < nlist ? order[(int64_t)s * nlist + i] : -1;
             const int c = l >= 0 ? cnt[(int64_t)s * nlist + l] : 0;
             const int ng = (c + qw - 1) / qw;
             sa[threadIdx.x] = ng;
@@ -601,22 +646,21 @@ __global__ __launch_bounds__(1024) void group_scan_kernel(const int32_t *cnt, co
             const int ex = ucarry + sa[threadIdx.x] - ng;
             if (l >= 0) {
                 uoff[(int64_t)s * nlist + l] = ex;
-                const int xl = l & 7;
-                // the first list of XCD xl's range
-                const bool first = order ? (i == 0 || (order[(int64_t)s * nlist + i - 1] & 7) != xl) : l == xl;
-                if (first) xfirst[xl] = ex;
+                for (int x = 0; x < 8; ++x)
+                    if (xbs[x] == i) xfirst[x] = ex;
             }
             __syncthreads();
             if (threadIdx.x == 1023) ucarry += sa[1023];
             __syncthreads();
         }
         if (threadIdx.x == 0) {
-            int prev_end = ucarry;
-            for (int x = 7; x >= 0; --x) {
-                const int f = xfirst[x] >= 0 ? xfirst[x] : prev_end;
-                xoff[s * 8 + x] = f;
-                xcnt[s * 8 + x] = prev_end - f;
-                prev_end = f;
+            // empty ranges at the end start at the total
+            int first[9];
+            for (int x = 0; x < 8; ++x) first[x] = xfirst[x] >= 0 ? xfirst[x] : ucarry;
+            first[8] = ucarry;
+            for (int x = 0; x < 8; ++x) {
+                xoff[s * 8 + x] = first[x];
+                xcnt[s * 8 + x] = first[x + 1] - first[x];
             }
         }
         __syncthreads();
