@@ -183,28 +183,46 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(PF ? 2 :
                 // canonical order: the block's partial from zero, then S += partial.
                 // A query with no undecided pair in the tile is skipped by the
                 // whole wave; lanes of decided pairs compute along, without effect.
-                auto advance = [&](int jj) {
+                auto advance = [&](int jj, const float *qv) {
                     float pb = 0.f;
 #pragma unroll
                     for (int kk = 0; kk < DD; ++kk) {
-                        float df = o[kk] - qs[jj][kk];
+                        float df = o[kk] - qv[kk];
                         pb = __fmaf_rn(df, df, pb);
                     }
                     return S[jj] + pb;
                 };
                 if (d < D) {
+                    // the next query's block is read from LDS while the
+                    // current one is evaluated
+                    float qa[DD], qn[DD];
+                    float ta, tn = sm.thr[w][0];
+#pragma unroll
+                    for (int kk = 0; kk < DD; kk += 4)
+                        *reinterpret_cast<float4 *>(qn + kk) = *reinterpret_cast<const float4 *>(&qs[0][kk]);
 #pragma unroll
                     for (int jj = 0; jj < QW; ++jj) {
+#pragma unroll
+                        for (int kk = 0; kk < DD; ++kk) qa[kk] = qn[kk];
+                        ta = tn;
+                        if (jj + 1 < QW) {
+                            constexpr int one = 1;
+                            const int jn = jj + one < QW ? jj + one : jj;
+                            tn = sm.thr[w][jn];
+#pragma unroll
+                            for (int kk = 0; kk < DD; kk += 4)
+                                *reinterpret_cast<float4 *>(qn + kk) = *reinterpret_cast<const float4 *>(&qs[jn][kk]);
+                        }
                         if (am[jj] == 0) continue;
-                        const float s = advance(jj);
+                        const float s = advance(jj, qa);
                         S[jj] = s;
-                        am[jj] &= ~__ballot(s > sm.thr[w][jj]);
+                        am[jj] &= ~__ballot(s > ta);
                     }
                 } else {
 #pragma unroll
                     for (int jj = 0; jj < QW; ++jj) {
                         if (am[jj] == 0) continue;
-                        const float s = advance(jj);
+                        const float s = advance(jj, qs[jj]);
                         if (((am[jj] >> lane) & 1ull) && s <= sm.r2s[jj]) {
                             const int p = atomicAdd(&pcnt[jj], 1);
                             sm.pos[w][jj][p] = make_key(s, (uint32_t)a.ids[off + v]);
