@@ -57,6 +57,9 @@ template <int DT, int DD, int QW, bool PF, int W>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(PF ? 2 : 4))) void scan_kernel(ScanArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     using Smem = ScanSmem<DD, QW, W, PF ? 2 : 1>;
+    // dense phase: read the next query block ahead (registers allow it for one
+    // wave per workgroup, blocks of up to 16 coordinates and up to 8 queries)
+    constexpr bool QPIPE = W == 1 && DD <= 16 && QW <= 8;
     Smem &sm = *reinterpret_cast<Smem *>(smem_raw);
     float *coef = reinterpret_cast<float *>(smem_raw + sizeof(Smem));
     uint64_t *tk = reinterpret_cast<uint64_t *>(smem_raw + ((sizeof(Smem) + sizeof(float) * a.nb + 15) & ~(size_t)15));
@@ -192,7 +195,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(PF ? 2 :
                     }
                     return S[jj] + pb;
                 };
-                if (d < D) {
+                if (d < D && QPIPE) {
                     // the next query's block is read from LDS while the
                     // current one is evaluated
                     float qa[DD], qn[DD];
@@ -217,6 +220,14 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(PF ? 2 :
                         const float s = advance(jj, qa);
                         S[jj] = s;
                         am[jj] &= ~__ballot(s > ta);
+                    }
+                } else if (d < D) {
+#pragma unroll
+                    for (int jj = 0; jj < QW; ++jj) {
+                        if (am[jj] == 0) continue;
+                        const float s = advance(jj, qs[jj]);
+                        S[jj] = s;
+                        am[jj] &= ~__ballot(s > sm.thr[w][jj]);
                     }
                 } else {
 #pragma unroll
