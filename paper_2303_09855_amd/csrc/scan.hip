@@ -19,7 +19,8 @@
 //
 // Execution.  A unit runs on one wave.  Units are laid out XCD-major:
 // workgroup w serves the units of XCD (w mod 8), so every unit of a list lands
-// on the same XCD and shares that XCD's L2.  The list is cut into 64-vector
+// on the same XCD and shares that XCD's L2; each XCD owns a range of lists of
+// equal work (list_order_kernel).  The list is cut into 64-vector
 // tiles.  In a tile a lane owns one vector: while more than dense_frac of the
 // tile's (vector, query) pairs are alive, the lane keeps the vector's DD
 // coordinates of the current block in registers and walks the unit's queries

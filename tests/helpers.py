@@ -15,7 +15,7 @@ class Workload:
     """Raw inputs plus the oracle's FP64 rotated copies (no GPU involved)."""
 
     def __init__(self, model: str, n: int, nq: int, D: int, nlist: int, seed: int,
-                 latent: int = 64, noise: float = 0.1, kmeans_iters: int = 5):
+                 latent: int = 64, noise: float = 0.1, kmeans_iters: int = 5, kmeans: bool = True):
         self.n, self.nq, self.D, self.nlist = n, nq, D, nlist
         if model == "mix":
             self.x = sd.mixture(n, D, seed, 1000)
@@ -27,6 +27,12 @@ class Workload:
         if nlist == 1:
             self.cent = self.x.mean(axis=0, dtype=np.float64)[None, :].astype(np.float32)
             self.assign = np.zeros(n, dtype=np.int32)
+        elif not kmeans:
+            # row i in list i mod nlist; centres are the list means
+            self.assign = (np.arange(n) % nlist).astype(np.int32)
+            sums = np.zeros((nlist, D))
+            np.add.at(sums, self.assign, self.x.astype(np.float64))
+            self.cent = (sums / np.bincount(self.assign, minlength=nlist)[:, None]).astype(np.float32)
         else:
             self.cent, self.assign = sd.clustering(self.x, nlist, seed + 3, iters=kmeans_iters)
         # oracle side

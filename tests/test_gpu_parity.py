@@ -186,6 +186,29 @@ def test_search_adsampling_recall_matches_oracle(ads, request, fixture, nprobe, 
     assert st[1] < 0.6 * st[0] * w.D
 
 
+def test_search_with_more_lists_than_one_xcd_range_sorts(ads):
+    """36,000 lists: some XCD range of every sweep holds more lists than the
+    in-LDS ordering sorts (those keep list-id order).  Unit order changes no
+    result, so the full scan still equals the oracle's."""
+    w = Workload("mix", 72_000, 32, 32, 36_000, 4002, kmeans=False)
+    ix = _build(ads, w, dd=16)
+    nprobe, K = 256, 10
+    ids, dist, probes = ads.search(ix, w.q, K, nprobe, eps0=math.inf, want_probes=True)
+    ids, dist, probes = _np(ids), _np(dist), _np(probes)
+    # many centres are nearly equidistant here: the probe sets must agree
+    # outside the tie band, and the oracle then scans the GPU's probe lists
+    _check_probes(w, probes, nprobe)
+    o_ids, o_d, _ = w.oracle_search(probes, K, math.inf, 16, method=oracle.METHOD_FDS)
+    for i in range(w.nq):
+        assert tie_band_equal(ids[i], dist[i], o_ids[i], o_d[i]), i
+    # ADSampling examines the same candidates as the oracle
+    stats = torch.zeros(ads.NSTATS, dtype=torch.int64, device="cuda")
+    ads.search(ix, w.q, K, nprobe, eps0=2.1, stats=stats)
+    _, _, o_st = w.oracle_search(probes, K, 2.1, 16)
+    assert _np(stats)[0] == o_st[:, 0].sum()
+    ix.free()
+
+
 def test_search_is_batch_independent_with_uneven_k_and_nprobe(ads, ivf128):
     """A query's result depends only on itself: run alone or in an uneven
     batch (per-query K and nprobe), the outputs are bit-identical."""
