@@ -704,7 +704,7 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
         int32_t *xb = reinterpret_cast<int32_t *>(ws + L.off_xb);
         hipLaunchKernelGGL(list_order_kernel, dim3(8 * L.nsweep), dim3(512), 0, stream, cnt, ix->list_off, nlist,
                            order, xb);
-        hipLaunchKernelGGL(group_scan_kernel, dim3(1), dim3(1024), 0, stream, cnt, order, xb, L.nsweep, nlist, qw,
+        hipLaunchKernelGGL(group_scan_kernel, dim3(L.nsweep), dim3(1024), 0, stream, cnt, order, xb, L.nsweep, nlist, qw,
                            beg, uoff, xoff, xcnt);
         hipLaunchKernelGGL(group_scatter_kernel, dim3(grid_for((int64_t)nq * nprobe_max)), dim3(ADS_WG), 0, stream,
                            probes, npq, keff, nq, nprobe_max, nlist, L.lg, beg, cursor, qent);

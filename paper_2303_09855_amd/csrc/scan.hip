@@ -623,20 +623,32 @@ __global__ __launch_bounds__(512) void list_order_kernel(const int32_t *cnt, con
     for (int j = t; j < n; j += blockDim.x) ord[j] = start + (int)(key[j] & 0xffffffu);
 }
 
-// One workgroup of 1024 threads.  Per sweep: exclusive prefix of cnt over
-// lists (entry offsets into qent, continuing across sweeps) and the unit
-// offsets of every list in the XCD-major order of list_order_kernel
-// (ceil(cnt / qw) units per list), with the first unit and the unit count of
-// every XCD.
+// One workgroup of 1024 threads per sweep: exclusive prefix of cnt over
+// lists (entry offsets into qent, continuing across sweeps: the workgroup
+// first counts the entries of the earlier sweeps) and the unit offsets of
+// every list in the XCD-major order of list_order_kernel (ceil(cnt / qw)
+// units per list), with the first unit and the unit count of every XCD.
 __global__ __launch_bounds__(1024) void group_scan_kernel(const int32_t *cnt, const int32_t *order, const int32_t *xb,
                                                           int nsweep, int nlist, int qw, int32_t *beg, int32_t *uoff,
                                                           int32_t *xoff, int32_t *xcnt) {
     __shared__ int32_t sa[1024];
     __shared__ int32_t carry;
     __shared__ int32_t xfirst[9];
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int s = 0; s < nsweep; ++s) {
+    const int s = blockIdx.x;
+    if (s >= nsweep) return;
+    {
+        int c = 0;
+        for (int64_t i = threadIdx.x; i < (int64_t)s * nlist; i += 1024) c += cnt[i];
+        sa[threadIdx.x] = c;
+        __syncthreads();
+        for (int o = 512; o > 0; o >>= 1) {
+            if (threadIdx.x < o) sa[threadIdx.x] += sa[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) carry = sa[0];
+        __syncthreads();
+    }
+    {
         // entry offsets in natural list order
         for (int l0 = 0; l0 < nlist; l0 += 1024) {
             const int l = l0 + threadIdx.x;
