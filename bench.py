@@ -32,8 +32,8 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 # published 157.3 TFLOP/s counts packed FP32.
 FP32_VALU_PEAK_TFLOPS = 78.6
 
-NPROBE_GRID = [8, 16, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096,
-               6144, 8192]
+NPROBE_GRID = [8, 16, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096]
+NPROBE_LIMIT = 4096            # the library's largest nprobe_max
 
 
 def log(msg: str) -> None:
@@ -161,7 +161,8 @@ def main() -> int:
             r = recall_at(args.nprobe, eps0)
             log(f"{label}: nprobe {args.nprobe:5d} recall@{K} {r:.4f} (fixed)")
             return args.nprobe, r
-        grid = [p for p in NPROBE_GRID if p < w.nlist] + [w.nlist]
+        top = min(w.nlist, NPROBE_LIMIT)
+        grid = [p for p in NPROBE_GRID if p < top] + [top]
         best = None
         for p in grid:
             r = recall_at(p, eps0)

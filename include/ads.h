@@ -232,7 +232,8 @@ ads_status ads_dco_batch_ip(const ads_index *ix, const float *q, const int64_t *
  *   K         device [nq] int32 per-query K in [0, k_max], or NULL for k_max.
  *   nprobe    device [nq] int32 per-query N_probe in [1, nprobe_max], or NULL
  *             for nprobe_max.  Per-query values above nprobe_max are clamped.
- *   k_max     >= 1; nprobe_max in [1, nlist].
+ *   k_max     >= 1; nprobe_max in [1, nlist] and at most 4096 (above:
+ *             ADS_EUNSUPPORTED).
  *   eps0      >= 0, +INF selects FDScanning (no statistical test).
  *   method    ads_method (PDScanning compares partial rotated distances).
  *   rerank    0: plain search.  1: low-precision mode: scan with a KNN set of

@@ -14,6 +14,7 @@ __global__ void setup_kernel(const int32_t *K, const int32_t *nprobe, int nq, in
                              int nprobe_max, int kfactor, int kcap, int32_t *kq, int32_t *keff,
                              int32_t *npq, float *r2, uint64_t *tk);
 __global__ void zero_i32_kernel(int32_t *p, int64_t n);
+size_t probe_select_smem(int nlist, int nprobe_max);
 __global__ void probe_select_kernel(const float *qrot, const float *dots, const float *cnorm, int D,
                                     int nlist, int nprobe_max, int32_t *probes);
 __global__ void group_count_kernel(const int32_t *probes, const int32_t *npq, const int32_t *keff,
@@ -177,7 +178,8 @@ constexpr int64_t PREFETCH_UNITS = ADS_PREFETCH_UNITS;
 #define ADS_WIDE_SWEEPS 2
 #endif
 constexpr int WIDE_SWEEPS = ADS_WIDE_SWEEPS;
-constexpr int NPROBE_MAX_LIMIT = 8192;
+// probe selection sorts the nprobe_max nearest centre keys in LDS (32 KB at 4096)
+constexpr int NPROBE_MAX_LIMIT = 4096;
 
 struct SearchLayout {
     size_t off_qrot, off_qunit, off_qbn, off_order, off_xb, off_dots, off_probes, off_kq, off_keff, off_npq, off_r2, off_tk, off_cnt,
@@ -690,7 +692,7 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
     {
         PhaseTimer t(ADS_PHASE_PROBE, stream);
         SEARCH_TRY(gemm_nt_f32(qrot, D, ix->cent_rot, D, dots, nlist, nq, nlist, D, stream), "centre products");
-        const size_t sh = sizeof(uint64_t) * (size_t)next_pow2(nprobe_max);
+        const size_t sh = probe_select_smem(nlist, nprobe_max);
         hipLaunchKernelGGL(probe_select_kernel, dim3(nq), dim3(ADS_WG), sh, stream, qrot, dots, ix->cent_norm, D,
                            nlist, nprobe_max, probes);
         SEARCH_TRY(hipGetLastError(), "probe selection");

@@ -121,38 +121,61 @@ __device__ __forceinline__ void lds_bitonic_sort(uint64_t *buf, int n) {
 
 // ---------------------------------------------------------------------------
 // Workgroup radix select: the k-th smallest (1-based) of n uint64 keys produced
-// by get(i), 8 passes of 8 bits from the most significant byte.
-// hist: LDS [256] uint32; misc: LDS [2] uint32.  All threads return the key.
-// Requires 1 <= k <= n.
+// by get(i), passes of 8 bits from the most significant byte; it stops early
+// once a single key carries the selected prefix.  The workgroup has 256
+// threads (one histogram bin each).  hist: LDS [256] uint32; misc: LDS [8]
+// uint32.  All threads return the key.  Requires 1 <= k <= n.
 // ---------------------------------------------------------------------------
 template <class Get>
 __device__ uint64_t radix_kth(Get get, int n, int k, uint32_t *hist, uint32_t *misc) {
+    __shared__ uint64_t found;
     uint64_t prefix = 0, pmask = 0;
     uint32_t kk = (uint32_t)k;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     for (int shift = 56; shift >= 0; shift -= 8) {
-        hist[threadIdx.x] = 0;
+        hist[t] = 0;
         __syncthreads();
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        for (int i = t; i < n; i += blockDim.x) {
             uint64_t key = get(i);
             if ((key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t acc = 0, sel = 255;
-            for (uint32_t d = 0; d < 256; ++d) {
-                uint32_t h = hist[d];
-                if (acc + h >= kk) { sel = d; break; }
-                acc += h;
-            }
-            misc[0] = sel;
-            misc[1] = kk - acc;
+        // inclusive prefix over the bins (within each wave, then across waves);
+        // the bin holding the kk-th key is the one whose range covers kk
+        const uint32_t h = hist[t];
+        uint32_t x = h;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) misc[4 + wv] = x;
+        __syncthreads();
+        uint32_t base = 0;
+        for (int w2 = 0; w2 < wv; ++w2) base += misc[4 + w2];
+        const uint32_t incl = base + x, excl = incl - h;
+        if (excl < kk && incl >= kk) {
+            misc[0] = (uint32_t)t;
+            misc[1] = kk - excl;
+            misc[2] = h;
         }
         __syncthreads();
-        uint32_t sel = misc[0];
+        const uint32_t sel = misc[0], cnt = misc[2];
         kk = misc[1];
         prefix |= (uint64_t)sel << shift;
         pmask |= (uint64_t)0xff << shift;
         __syncthreads();
+        if (cnt == 1) {
+            // one key carries the prefix: it is the k-th
+            for (int i = t; i < n; i += blockDim.x) {
+                uint64_t key = get(i);
+                if ((key & pmask) == prefix) found = key;
+            }
+            __syncthreads();
+            const uint64_t r = found;
+            __syncthreads();
+            return r;
+        }
     }
     return prefix;
 }

@@ -479,13 +479,26 @@ __global__ void zero_i32_kernel(int32_t *p, int64_t n) {
 // squared distance ||q'||^2 + ||c'||^2 - 2 q'.c' (clamped at 0), ascending by
 // (distance, list id).
 // ---------------------------------------------------------------------------
+// The keys of one query stay in LDS for the selection passes when they fit
+// beside the sorted output (at most 60 KB of keys in all).
+__host__ __device__ inline bool probe_keys_cached(int nlist, int nprobe_max) {
+    return next_pow2(nprobe_max) + nlist <= 7680;
+}
+size_t probe_select_smem(int nlist, int nprobe_max) {
+    return sizeof(uint64_t) *
+           ((size_t)next_pow2(nprobe_max) + (probe_keys_cached(nlist, nprobe_max) ? (size_t)nlist : 0));
+}
+
 __global__ __launch_bounds__(ADS_WG) void probe_select_kernel(
     const float *qrot, const float *dots, const float *cnorm, int D, int nlist, int nprobe_max,
     int32_t *probes) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int k = nprobe_max;
+    const int P = next_pow2(k);
     uint64_t *buf = reinterpret_cast<uint64_t *>(smem_raw);
+    uint64_t *kc = buf + P;            // the keys, when probe_keys_cached
     __shared__ uint32_t hist[256];
-    __shared__ uint32_t misc[4];
+    __shared__ uint32_t misc[8];
     __shared__ float red[ADS_WG / 64];
     const int q = blockIdx.x;
     const float *qr = qrot + (int64_t)q * D;
@@ -496,13 +509,17 @@ __global__ __launch_bounds__(ADS_WG) void probe_select_kernel(
     __syncthreads();
     const float qn = red[0] + red[1] + red[2] + red[3];
     const float *dq = dots + (int64_t)q * nlist;
-    auto get = [&](int i) -> uint64_t {
+    auto key_of = [&](int i) -> uint64_t {
         float s = qn + cnorm[i] - 2.f * dq[i];
         s = s > 0.f ? s : 0.f;
         return make_key(s, (uint32_t)i);
     };
-    const int k = nprobe_max;
-    const int P = next_pow2(k);
+    const bool cached = probe_keys_cached(nlist, nprobe_max);
+    if (cached) {
+        for (int i = threadIdx.x; i < nlist; i += ADS_WG) kc[i] = key_of(i);
+        __syncthreads();
+    }
+    auto get = [&](int i) -> uint64_t { return cached ? kc[i] : key_of(i); };
     uint64_t kth = KEY_NONE;
     if (k < nlist) kth = radix_kth(get, nlist, k, hist, misc);
     if (threadIdx.x == 0) misc[2] = 0;
@@ -752,7 +769,7 @@ __global__ __launch_bounds__(ADS_WG) void merge_kernel(const uint64_t *slots, co
     extern __shared__ __align__(16) unsigned char smem_raw[];
     uint64_t *buf = reinterpret_cast<uint64_t *>(smem_raw);
     __shared__ uint32_t hist[256];
-    __shared__ uint32_t misc[4];
+    __shared__ uint32_t misc[8];
     const int q = blockIdx.x;
     const int K = keff[q];
     const int hi = min(rank_b, npq[q]);

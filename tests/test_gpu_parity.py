@@ -188,11 +188,14 @@ def test_search_adsampling_recall_matches_oracle(ads, request, fixture, nprobe, 
 
 def test_search_with_more_lists_than_one_xcd_range_sorts(ads):
     """36,000 lists: some XCD range of every sweep holds more lists than the
-    in-LDS ordering sorts (those keep list-id order).  Unit order changes no
-    result, so the full scan still equals the oracle's."""
+    in-LDS ordering sorts (those keep list-id order), and probe selection
+    keeps its keys outside LDS.  Unit order changes no result, so the full
+    scan still equals the oracle's; nprobe_max is the largest supported."""
     w = Workload("mix", 72_000, 32, 32, 36_000, 4002, kmeans=False)
     ix = _build(ads, w, dd=16)
-    nprobe, K = 256, 10
+    nprobe, K = 4096, 10
+    with pytest.raises(ads.AdsError):
+        ads.search(ix, w.q, K, 4097)
     ids, dist, probes = ads.search(ix, w.q, K, nprobe, eps0=math.inf, want_probes=True)
     ids, dist, probes = _np(ids), _np(dist), _np(probes)
     # many centres are nearly equidistant here: the probe sets must agree
