@@ -32,7 +32,10 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 # published 157.3 TFLOP/s counts packed FP32.
 FP32_VALU_PEAK_TFLOPS = 78.6
 
-NPROBE_GRID = [8, 16, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096]
+# operating-point search: the smallest grid nprobe that reaches the recall target
+# (steps of 1/8 between 512 and 1024)
+NPROBE_GRID = [8, 16, 32, 48, 64, 96, 128, 192, 256, 384, 512, 576, 640, 704, 768, 896, 1024, 1536, 2048,
+               3072, 4096]
 NPROBE_LIMIT = 4096            # the library's largest nprobe_max
 
 
