@@ -70,9 +70,6 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device-to-device copy first (reference kernel "
                          "of known size for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
-    ap.add_argument("--dense-form", type=int, default=None, choices=[0, 1],
-                    help="dense phase of the ADSampling scan: 0 = canonical register tiles, "
-                         "1 = dot form on the matrix cores (same results; default: the library's)")
     ap.add_argument("--tune", default="",
                     help="scan scheduling knobs, e.g. sweep_log2=4,dense_frac=0.25 (ads_tuning fields)")
     ap.add_argument("--nprobe", type=int, default=None,
@@ -107,7 +104,7 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     ads.load()
-    knobs = {} if args.dense_form is None else {"dense_form": args.dense_form}
+    knobs = {}
     for kv in filter(None, args.tune.split(",")):
         k, v = kv.split("=")
         knobs[k.strip()] = float(v) if k.strip() == "dense_frac" else int(v)
@@ -223,7 +220,7 @@ def main() -> int:
     achieved_gbs = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
     flops = 3.0 * dims  # one subtract and one fused multiply-add per sampled coordinate
     achieved_tflops = flops / (scan_ms_step * 1e-3) / 1e12
-    scan_kernel = "scan_mfma_kernel" if ads.get_tuning()["dense_form"] == 1 else "scan_kernel"
+    scan_kernel = "scan_kernel"
     traffic = scan_traffic_from_profile(scan_kernel)
 
     cpu = None
@@ -315,8 +312,7 @@ def serve(args, w, ix, q, gt, x):
 # Sources the scan kernels are compiled from (the counter summary records
 # their digest; a changed kernel invalidates the traffic figure).
 SCAN_SOURCES = {
-    "scan_kernel": ["scan.hip", "scan_sparse.h", "common.h", "kernels.h"],
-    "scan_mfma_kernel": ["scan_mfma.hip", "scan_sparse.h", "common.h", "kernels.h"],
+    "scan_kernel": ["scan_kernel.h", "scan_sparse.h", "common.h", "kernels.h"],
 }
 
 

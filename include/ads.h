@@ -143,9 +143,6 @@ ads_status ads_rotate(const float *P, int32_t D, const float *X, int64_t n, floa
  * (all vectors' first block contiguous, then the second block, ...): the
  * cache-friendly arrangement of Section 5.2 generalised from two arrays to
  * one array per block.  Within a list, vectors keep ascending id order.
- * The index also holds the float32 squared norm of every stored block and of
- * every stored vector (4 (D/delta_d + 1) bytes per vector), which the
- * matrix-core scan uses for its dot-product form and rounding margins.
  * Synchronises the stream once (the list sizes are needed on the host).
  * Errors: ADS_EINVAL (sizes, ids out of range), ADS_ENOMEM, ADS_EHIP.
  */
@@ -260,7 +257,7 @@ ads_status ads_search(const ads_index *ix, const float *q, int32_t nq, const int
 
 /* ads_search_workspace_size -- HOST: bytes of workspace ads_search needs for
  * these sizes under the calling thread's queries_per_unit setting, for any
- * method, eps0 and dense_form (0 on invalid arguments, with ads_last_error set). */
+ * method and eps0 (0 on invalid arguments, with ads_last_error set). */
 uint64_t ads_search_workspace_size(const ads_index *ix, int32_t nq, int32_t k_max,
                                    int32_t nprobe_max, int32_t rerank);
 
@@ -304,18 +301,16 @@ typedef struct {
                                  pairs is alive; 0 = automatic (0.25 for delta_d <= 16,
                                  0.125 otherwise).  Default 0. */
     int32_t queries_per_unit; /* 1, 2, 4, 8 or 16 queries per work unit; 0 = the largest
-                                 power of two up to 8 (16 with dense_form 1) whose KNN sets fit
-                                 in 4 KB of LDS.  Default 0. */
+                                 power of two up to 8 whose KNN sets fit in 4 KB of LDS.
+                                 Default 0. */
     int32_t sweep_log2;       /* probe ranks are scanned in sweeps [0,1), [1,g), [g,g^2), ...
                                  with g = 2^sweep_log2, sweep_log2 in [1, 6].  Default 4. */
     int32_t grid_per_xcd;     /* persistent scan workgroups per XCD, 0 = as many as the
                                  sweep has units (capped at 4096).  Default 0. */
-    int32_t dense_form;       /* dense phase of ADSampling / PDScanning scans: 0 = register
-                                 tiles, canonical form (subtract, square, add); 1 = dot-product
-                                 form on the matrix cores, which decides only where a
-                                 worst-case rounding bound settles the decision and re-runs
-                                 every other pair in the canonical form (same results as 0).
-                                 FDScanning always uses 0.  Default 0. */
+    int32_t prefetch_units;   /* sweeps with fewer work units than this (and one wave per
+                                 unit) run the scan instantiation that fetches block b+1 while
+                                 block b is evaluated; 0 = 8192.  Same results either way.
+                                 Default 0. */
 } ads_tuning;
 
 /* ads_set_tuning / ads_get_tuning -- HOST, per thread: knobs for later

@@ -35,7 +35,7 @@ PHASES = ["rotate", "probe", "group", "scan", "merge", "output"]
 class Tuning(ctypes.Structure):
     _fields_ = [("dense_frac", ctypes.c_float), ("queries_per_unit", ctypes.c_int32),
                 ("sweep_log2", ctypes.c_int32), ("grid_per_xcd", ctypes.c_int32),
-                ("dense_form", ctypes.c_int32)]
+                ("prefetch_units", ctypes.c_int32)]
 
 
 class AdsError(RuntimeError):
@@ -312,14 +312,14 @@ def get_tuning() -> dict:
 
 def set_tuning(**kw) -> None:
     """Update the calling thread's scan knobs (dense_frac, queries_per_unit,
-    sweep_log2, grid_per_xcd, dense_form); unspecified ones keep their value."""
+    sweep_log2, grid_per_xcd, prefetch_units); unspecified ones keep their value."""
     cur = get_tuning()
     unknown = set(kw) - set(cur)
     if unknown:
         raise ValueError(f"unknown tuning fields {sorted(unknown)}")
     cur.update({k: v for k, v in kw.items() if v is not None})
     t = Tuning(float(cur["dense_frac"]), int(cur["queries_per_unit"]), int(cur["sweep_log2"]),
-               int(cur["grid_per_xcd"]), int(cur["dense_form"]))
+               int(cur["grid_per_xcd"]), int(cur["prefetch_units"]))
     _check(load().ads_set_tuning(ctypes.byref(t)))
 
 

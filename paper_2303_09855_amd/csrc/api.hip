@@ -55,8 +55,6 @@ struct ads_index {
     int32_t *list_of_pos = nullptr;  // [n]
     void *data = nullptr;        // blocked layout
     float *rows32 = nullptr;     // [n][D] float32 rows in stored order (optional)
-    float *blk_norm = nullptr;   // per list [nb][nl] squared block norms (blocked order)
-    float *vec_norm = nullptr;   // [n] squared norms in stored order
     int64_t bytes = 0;
 };
 
@@ -132,7 +130,7 @@ bool valid_dd(int dd) { return dd == 8 || dd == 16 || dd == 32 || dd == 64; }
 void free_index(ads_index *ix) {
     if (!ix) return;
     void *ptrs[] = {ix->P, ix->cent_rot, ix->cent_norm, ix->list_off, ix->ids, ix->pos_of,
-                    ix->list_of_pos, ix->data, ix->rows32, ix->norms, ix->blk_norm, ix->vec_norm};
+                    ix->list_of_pos, ix->data, ix->rows32, ix->norms};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete ix;
@@ -155,10 +153,10 @@ unsigned grid_for(int64_t n, int64_t cap = 65536) {
 }
 
 // Queries per scan unit for a KNN-set capacity (local KNN sets <= 4 KB of LDS),
-// or the tuned value when it fits.  The matrix-core scan fills 16 query slots.
-int qw_for(int kcap, bool mfma) {
+// or the tuned value when it fits.
+int qw_for(int kcap) {
     int auto_qw = 1;
-    for (int qw = mfma ? 16 : 8; qw > 1; qw >>= 1)
+    for (int qw = 8; qw > 1; qw >>= 1)
         if (qw * kcap <= 512) { auto_qw = qw; break; }
     const int t = g_tune.queries_per_unit;
     if (t > 0 && t * kcap <= 4096) return t;
@@ -166,11 +164,9 @@ int qw_for(int kcap, bool mfma) {
 }
 
 constexpr int KCAP_MAX = 512;
-// Sweeps with fewer work units than this run the prefetching register scan.
-#ifndef ADS_PREFETCH_UNITS
-#define ADS_PREFETCH_UNITS 8192
-#endif
-constexpr int64_t PREFETCH_UNITS = ADS_PREFETCH_UNITS;
+// Default of the prefetch_units knob: sweeps with fewer work units than this
+// run the prefetching scan instantiation.
+constexpr int64_t PREFETCH_UNITS = 8192;
 // The first sweeps update thresholds once per round of four tiles (the
 // register scan runs them with four waves per unit): more parallel work in
 // the sweeps that have few units.
@@ -182,34 +178,18 @@ constexpr int WIDE_SWEEPS = ADS_WIDE_SWEEPS;
 constexpr int NPROBE_MAX_LIMIT = 4096;
 
 struct SearchLayout {
-    size_t off_qrot, off_qunit, off_qbn, off_order, off_xb, off_dots, off_probes, off_kq, off_keff, off_npq, off_r2, off_tk, off_cnt,
+    size_t off_qrot, off_qunit, off_order, off_xb, off_dots, off_probes, off_kq, off_keff, off_npq, off_r2, off_tk, off_cnt,
         off_beg, off_cursor, off_uoff, off_xoff, off_xcnt, off_units, off_qent, off_slots, total;
     int nsweep, kcap, qw, lg;
-    bool mfma, qnorms;               // matrix-core scan; query block norms needed
     int64_t ucap;
 };
 
-// The matrix-core scan serves the methods with finite test coefficients.
-// dense_form 1 (matrix cores) serves the methods with finite test
-// coefficients; FDScanning keeps the canonical form.
-int dense_form_for(float eps0, int method) {
-    if (g_tune.dense_form == 0 || method == ADS_METHOD_FDSCANNING) return 0;
-    if (method == ADS_METHOD_ADSAMPLING && std::isinf(eps0)) return 0;
-    return g_tune.dense_form;
-}
-bool use_mfma(float eps0, int method) {
-    if (g_tune.dense_form != 1 || method == ADS_METHOD_FDSCANNING) return false;
-    return !(method == ADS_METHOD_ADSAMPLING && std::isinf(eps0));
-}
-
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-SearchLayout layout_for(const ads_index *ix, int nq, int k_max, int nprobe_max, int rerank, bool mfma, bool qnorms) {
+SearchLayout layout_for(const ads_index *ix, int nq, int k_max, int nprobe_max, int rerank) {
     SearchLayout L{};
     L.kcap = k_max * (rerank ? 4 : 1);
-    L.mfma = mfma;
-    L.qnorms = qnorms;
-    L.qw = qw_for(L.kcap, mfma);
+    L.qw = qw_for(L.kcap);
     L.lg = g_tune.sweep_log2;
     L.nsweep = num_sweeps(nprobe_max, L.lg);
     size_t o = 0;
@@ -217,7 +197,6 @@ SearchLayout layout_for(const ads_index *ix, int nq, int k_max, int nprobe_max, 
     const size_t nqs = (size_t)(nq > 0 ? nq : 1);
     L.off_qrot = take(nqs * ix->D * sizeof(float));
     L.off_qunit = take(ix->metric == ADS_METRIC_COSINE ? nqs * ix->D * sizeof(float) : 0);
-    L.off_qbn = take(qnorms ? nqs * (ix->nb + 1) * sizeof(float) : 0);
     L.off_dots = take(nqs * ix->nlist * sizeof(float));
     L.off_probes = take(nqs * nprobe_max * sizeof(int32_t));
     L.off_kq = take(nqs * sizeof(int32_t));
@@ -451,8 +430,6 @@ extern "C" ads_status ads_ivf_build(const float *base, int64_t n, int32_t D, con
         BUILD_TRY(e, "alloc blocked layout");
     }
     if (keep_fp32) BUILD_TRY(dmalloc(&ix->rows32, (size_t)n * D, &ix->bytes), "alloc float32 rows");
-    BUILD_TRY(dmalloc(&ix->blk_norm, (size_t)n * (D / delta_d), &ix->bytes), "alloc block norms");
-    BUILD_TRY(dmalloc(&ix->vec_norm, (size_t)n, &ix->bytes), "alloc vector norms");
     BUILD_TRY(hipMalloc(&rot, sizeof(float) * (size_t)n * D), "alloc rotation scratch");
     if (metric == ADS_METRIC_COSINE) {
         BUILD_TRY(dmalloc(&ix->norms, (size_t)n, &ix->bytes), "alloc norms");
@@ -474,8 +451,6 @@ extern "C" ads_status ads_ivf_build(const float *base, int64_t n, int32_t D, con
     BUILD_TRY(gemm_nt_f32(src, D, ix->P, D, rot, D, n, D, D, stream), "rotate base");
     BUILD_TRY(launch_pack(storage, rot, ix->ids, ix->list_of_pos, ix->list_off, n, D, delta_d, ix->data,
                           ix->rows32, stream), "pack lists");
-    BUILD_TRY(launch_block_norms(storage, ix->data, ix->list_of_pos, ix->list_off, n, D, delta_d, ix->blk_norm,
-                                 ix->vec_norm, stream), "block norms");
     const float *csrc = centroids;
     if (metric == ADS_METRIC_COSINE) {
         BUILD_TRY(hipStreamSynchronize(stream), "synchronize");   // unit is reused below
@@ -599,13 +574,7 @@ extern "C" ads_status ads_dco_batch_ip(const ads_index *ix, const float *q, cons
 extern "C" uint64_t ads_search_workspace_size(const ads_index *ix, int32_t nq, int32_t k_max,
                                               int32_t nprobe_max, int32_t rerank) {
     if (check_search_args(ix, nq, k_max, nprobe_max, rerank) != ADS_OK) return 0;
-    // large enough for either scan variant (the method and eps0 pick one)
-    size_t best = 0;
-    for (int f = 0; f < 2; ++f) {
-        const size_t t = layout_for(ix, nq, k_max, nprobe_max, rerank, f == 1, f != 0).total;
-        if (t > best) best = t;
-    }
-    return (uint64_t)best;
+    return (uint64_t)layout_for(ix, nq, k_max, nprobe_max, rerank).total;
 }
 
 extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq, const int32_t *K,
@@ -623,8 +592,7 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
     HIP_TRY(hipGetLastError(), "pending HIP error");
 
     const int eff_method = std::isinf(eps0) && method == ADS_METHOD_ADSAMPLING ? ADS_METHOD_FDSCANNING : method;
-    const int form = dense_form_for(eps0, eff_method);
-    const SearchLayout L = layout_for(ix, nq, k_max, nprobe_max, rerank, form == 1, form != 0);
+    const SearchLayout L = layout_for(ix, nq, k_max, nprobe_max, rerank);
     const int qw = L.qw;
     const int D = ix->D, nlist = ix->nlist;
     unsigned char *ws = reinterpret_cast<unsigned char *>(workspace);
@@ -684,9 +652,6 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
             qsrc = qunit;
         }
         SEARCH_TRY(gemm_nt_f32(qsrc, D, ix->P, D, qrot, D, nq, D, D, stream), "rotate queries");
-        if (L.qnorms)
-            SEARCH_TRY(launch_query_block_norms(qrot, nq, D, ix->dd, reinterpret_cast<float *>(ws + L.off_qbn), stream),
-                       "query block norms");
     }
     // 2. probe selection
     {
@@ -742,10 +707,6 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
         // test, so it is kept longer (measured best on the D = 960 workload)
         a.dense_frac = g_tune.dense_frac > 0.f ? g_tune.dense_frac : (ix->dd <= 16 ? 0.25f : 0.125f);
         a.round_tiles = s < WIDE_SWEEPS ? 4 : 1;
-        a.blk_norm = ix->blk_norm;
-        a.vec_norm = ix->vec_norm;
-        a.qbn = reinterpret_cast<const float *>(ws + L.off_qbn);
-        a.kappa = scan_margin_kappa(ix->dd, ix->nb);
         // persistent grid: 8 XCD lanes x P workgroups, P bounded by the units of the sweep
         const int64_t pairs = (int64_t)nq * (rb - ra);
         const int64_t units_bound = (pairs + qw - 1) / qw + (pairs < nlist ? pairs : nlist);
@@ -755,11 +716,9 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
         if (P < 1) P = 1;
         {
             PhaseTimer t(ADS_PHASE_SCAN, stream);
-            if (L.mfma)
-                SEARCH_TRY(launch_scan_mfma(a, ix->storage, ix->dd, qw, (int)(8 * P), stream), "scan");
-            else
-                SEARCH_TRY(launch_scan(a, ix->storage, ix->dd, qw, (int)(8 * P), units_bound < PREFETCH_UNITS,
-                                       a.round_tiles == 4, stream), "scan");
+            const int64_t pf_units = g_tune.prefetch_units > 0 ? g_tune.prefetch_units : PREFETCH_UNITS;
+            SEARCH_TRY(launch_scan(a, ix->storage, ix->dd, qw, (int)(8 * P), units_bound < pf_units,
+                                   a.round_tiles == 4, stream), "scan");
         }
         const size_t sh = sizeof(uint64_t) * (size_t)next_pow2(L.kcap);
         PhaseTimer tm(ADS_PHASE_MERGE, stream);
@@ -864,8 +823,8 @@ extern "C" ads_status ads_set_tuning(const ads_tuning *t) {
         return fail(ADS_EINVAL, "sweep_log2 must be in [1, 6] (got %d)", t->sweep_log2);
     if (t->grid_per_xcd < 0 || t->grid_per_xcd > 65536)
         return fail(ADS_EINVAL, "grid_per_xcd must be in [0, 65536] (got %d)", t->grid_per_xcd);
-    if (t->dense_form != 0 && t->dense_form != 1)
-        return fail(ADS_EINVAL, "dense_form must be 0 or 1 (got %d)", t->dense_form);
+    if (t->prefetch_units < 0)
+        return fail(ADS_EINVAL, "prefetch_units must be >= 0 (got %d)", t->prefetch_units);
     g_tune = *t;
     return ADS_OK;
 }

@@ -25,23 +25,14 @@ struct ScanArgs {
     int nprobe_max, kcap, D, nb;
     float dense_frac;       // pairs alive at or below this fraction (<= 0.25) switch to the pair list
     int round_tiles;        // 64-vector tiles per threshold update (4 in the first sweeps, else 1)
-    // matrix-core scan only
-    const float *blk_norm;  // per list [nb][nl]: squared norm of each stored block
-    const float *vec_norm;  // [n] squared norm of each stored vector, by position
-    const float *qbn;       // [nq][nb + 1]: block norms of each rotated query, then its full norm
-    float kappa;            // margin factor of the dot-product form
 };
 
 hipError_t launch_scan(const ScanArgs &a, int dtype, int dd, int qw, int grid, bool prefetch, bool wide,
                        hipStream_t s);
-hipError_t launch_scan_mfma(const ScanArgs &a, int dtype, int dd, int qw, int grid, hipStream_t s);
-float scan_margin_kappa(int dd, int nb);
-
-// Squared norms of every stored block and vector of the blocked layout.
-hipError_t launch_block_norms(int dtype, const void *data, const int32_t *list_of_pos, const int64_t *list_off,
-                              int64_t n, int D, int dd, float *blk_norm, float *vec_norm, hipStream_t s);
-// Per-block and full squared norms of rows of x [n][D].
-hipError_t launch_query_block_norms(const float *x, int64_t n, int D, int dd, float *out, hipStream_t s);
+// One (storage type, block width) slice of the scan instantiations, defined in
+// scan_kernel.h and instantiated by scan_inst.hip (one object per slice).
+template <int DT, int DD>
+hipError_t launch_scan_q(const ScanArgs &a, int qw, int grid, bool pf, bool wide, hipStream_t s);
 
 int num_sweeps(int nprobe_max, int lg);
 int sweep_begin(int s, int lg);

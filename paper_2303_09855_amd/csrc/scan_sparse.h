@@ -1,5 +1,4 @@
-// The pair-list ("sparse") phase of the candidate scan, shared by the
-// register-dense scan and the matrix-core scan.
+// The pair-list ("sparse") phase of the candidate scan.
 //
 // A list holds (vector of the current 64-vector tile, query of the unit)
 // pairs that all stand at the same next block bcur, each with its partial
@@ -16,14 +15,8 @@
 // in block order, so a pair's S at every block is bit-identical to the
 // explicit-candidate DCO, whatever G is and whenever the pair entered a list.
 //
-// Two decision modes:
-//   exact  : S is canonical; reject iff S > coef(d) r^2 at d < D, positive iff
-//            S <= r^2 at d = D.
-//   margin : S carried into the list is an approximation of the canonical S
-//            within a per-pair bound m (it came from the dot-product form);
-//            a pair is rejected only when S - coef(d) r^2 > m, and leaves for
-//            the exact queue when the canonical decision cannot be read off
-//            (|S - coef(d) r^2| <= m, or d = D and S - r^2 <= m).
+// Decisions: reject iff S > coef(d) r^2 at d < D, positive iff S <= r^2 at
+// d = D.
 #pragma once
 #include "kernels.h"
 
@@ -100,25 +93,19 @@ struct SparseCtx {
     const float *r2s;             // [QW] thresholds (LDS)
     const float *coef;            // [nb] test coefficients (LDS)
     int D, nb;
-    // margin mode
-    const float *vmarg;           // [64] margin share of the tile's vectors (LDS)
-    const float *qmarg;           // [QW] margin share of the unit's queries (LDS)
-    uint16_t *exq;                // exact queue (LDS)
 };
 
 struct SparseOut {
     unsigned long long dims;      // this lane's sampled dimensions
     unsigned long long pos;       // this lane's positives
-    int nexq;                     // exact-queue length after the run (wave-uniform)
 };
 
 // Runs the pairs of list0[0..n) (all at block bcur) to their decisions, with
-// list0 / list1 as ping-pong buffers.  In exact mode a positive calls
-// sink(jj, s, vv) on the pair's leader lane; in margin mode undecidable pairs
-// are appended to ctx.exq from position nexq on.
-template <int DT, int DD, bool MARGIN, class Sink>
+// list0 / list1 as ping-pong buffers.  A positive calls sink(jj, s, vv) on the
+// pair's leader lane.
+template <int DT, int DD, class Sink>
 __device__ __forceinline__ SparseOut sparse_run(const SparseCtx &c, uint64_t *list0, uint64_t *list1, int n,
-                                                int bcur, int nexq, Sink sink) {
+                                                int bcur, Sink sink) {
     unsigned long long my_dims = 0, my_pos = 0;
     constexpr int EB = Elem<DT>::bytes;
     const int lane = threadIdx.x & 63;
@@ -158,42 +145,19 @@ __device__ __forceinline__ SparseOut sparse_run(const SparseCtx &c, uint64_t *li
             }
             const int d = (blk + 1) * DD;
             const float r2 = pv ? c.r2s[jj] : 0.f;
-            bool ev, unc = false;
-            if constexpr (MARGIN) {
-                const float m = pv ? c.vmarg[vv] + c.qmarg[jj] : 0.f;
-                if (!bv) {
-                    ev = false;
-                } else if (d < D) {
-                    const float dl = sb - c.coef[blk] * r2;
-                    const bool rej = dl > m;
-                    const bool keep = dl <= -m;
-                    unc = !rej && !keep;
-                    ev = !keep;
-                } else {
-                    const bool notpos = sb - r2 > m;
-                    unc = !notpos;
-                    ev = true;
-                }
-            } else {
-                ev = bv && d < D && test_reject(sb, c.coef[bv ? blk : 0], r2);
-            }
+            const bool ev = bv && d < D && test_reject(sb, c.coef[bv ? blk : 0], r2);
             const uint64_t rm = __ballot(ev);
-            const uint64_t um = __ballot(unc);
             const uint64_t gmask = ((1ull << G) - 1ull) << (lane & ~(G - 1));
             const uint64_t grm = rm & gmask;
             // the group's last block and the value of S there
             const int glast = min(G, nb - bcur) - 1;
             const float slast = __shfl(sb, (lane & ~(G - 1)) + glast, 64);
-            bool keep = false, push = false;
+            bool keep = false;
             if (pv && gi == 0) {
                 if (grm) {
                     const int first = __ffsll((long long)grm) - 1;       // lane index of the event
-                    if (MARGIN && ((um >> first) & 1ull)) {
-                        push = true;
-                    } else {
-                        my_dims += (unsigned long long)(bcur + first - (lane & ~(G - 1)) + 1) * DD;
-                    }
-                } else if (!MARGIN && bcur + glast + 1 >= nb) {
+                    my_dims += (unsigned long long)(bcur + first - (lane & ~(G - 1)) + 1) * DD;
+                } else if (bcur + glast + 1 >= nb) {
                     my_dims += D;
                     if (slast <= r2) {
                         sink(jj, slast, vv);
@@ -202,11 +166,6 @@ __device__ __forceinline__ SparseOut sparse_run(const SparseCtx &c, uint64_t *li
                 } else {
                     keep = true;
                 }
-            }
-            if constexpr (MARGIN) {
-                const uint64_t pm = __ballot(push);
-                if (push) c.exq[nexq + __popcll(pm & lanemask_lt)] = (uint16_t)(jj << 6 | vv);
-                nexq += __popcll(pm);
             }
             const uint64_t km = __ballot(keep);
             if (keep) {
@@ -219,7 +178,7 @@ __device__ __forceinline__ SparseOut sparse_run(const SparseCtx &c, uint64_t *li
         cur ^= 1;
         bcur += G;
     }
-    return SparseOut{my_dims, my_pos, nexq};
+    return SparseOut{my_dims, my_pos};
 }
 
 }  // namespace ads

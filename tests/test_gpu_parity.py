@@ -290,47 +290,60 @@ def test_search_distances_equal_dco_batch(ads, ivf960):
             assert np.array_equal(_np(d), dist[i][v])
 
 
-_MC_CASES = [
+# Scan forms: one wave per unit without prefetch (large sweeps), one wave per
+# unit fetching block b+1 while block b is evaluated (sweeps with few units),
+# and four waves per unit with rounds of four tiles (the first two sweeps).
+# prefetch_units = 1 makes every one-wave sweep take the plain form, 1 << 30
+# makes every one-wave sweep take the prefetching form; each query's result is
+# the same whichever form ran.
+_FORM_CASES = [
     # fixture, delta_d, storage, method, eps0, K, nprobe, queries_per_unit
+    ("ivf960", 16, 0, 0, 2.1, 10, 40, 0),
     ("ivf960", 32, 0, 0, 2.1, 10, 8, 0),
-    ("ivf960", 16, 0, 0, 1.0, 10, 8, 4),
     ("ivf960", 64, 1, 0, 2.1, 40, 8, 0),
     ("ivf960", 8, 2, 0, 2.1, 10, 6, 1),
     ("ivf128", 32, 0, 0, 2.1, 10, 16, 16),
-    ("ivf128", 16, 0, 2, 2.1, 10, 16, 0),
+    ("ivf128", 16, 0, 2, 2.1, 10, 40, 0),
     ("ivf128", 8, 0, 0, 0.5, 100, 8, 0),
-    ("ivf128", 32, 1, 0, 2.1, 10, 64, 8),
+    ("ivf128", 16, 1, 0, 2.1, 10, 64, 8),
 ]
 
 
-@pytest.mark.parametrize("fixture,dd,storage,method,eps0,K,nprobe,qpu", _MC_CASES)
-def test_dense_forms_give_identical_results(ads, request, fixture, dd, storage, method, eps0, K,
-                                            nprobe, qpu):
-    """The dot-product dense phase on the matrix cores (form 1) acts only on
-    decisions its rounding bound settles and sends every other pair through
-    the canonical form, so ids, distances and every statistic (DCOs, sampled
-    dimensions, positives) equal those of the canonical register scan
-    (form 0) bit for bit.  The mixture data of ivf128
-    sits far from the origin (norms ~20x the distances), which puts many
-    tests inside the rounding band."""
+@pytest.mark.parametrize("fixture,dd,storage,method,eps0,K,nprobe,qpu", _FORM_CASES)
+def test_scan_forms_give_identical_results(ads, request, fixture, dd, storage, method, eps0, K,
+                                           nprobe, qpu):
+    """The plain and the prefetching one-wave instantiations evaluate the same
+    canonical partial sums with the same thresholds, so ids, distances and every
+    statistic (DCOs, sampled dimensions, positives) are bit-identical; and the
+    ADSampling results match the oracle's recall (Corollary 4.2) in both."""
     w, _ = request.getfixturevalue(fixture)
     ix = _build(ads, w, dd=dd, storage=storage)
     saved = ads.get_tuning()
     res = {}
     try:
-        for form in (0, 1):
-            ads.set_tuning(dense_form=form, queries_per_unit=qpu)
+        for pf in (1, 1 << 30):
+            ads.set_tuning(prefetch_units=pf, queries_per_unit=qpu)
             stats = torch.zeros(ads.NSTATS, dtype=torch.int64, device="cuda")
-            ids, dist = ads.search(ix, w.q, K, nprobe, eps0=eps0, method=method, stats=stats)
-            res[form] = (_np(ids), _np(dist), _np(stats))
+            ids, dist, probes = ads.search(ix, w.q, K, nprobe, eps0=eps0, method=method, stats=stats,
+                                           want_probes=True)
+            res[pf] = (_np(ids), _np(dist), _np(stats), _np(probes))
     finally:
         ads.set_tuning(**saved)
         ix.free()
-    for form in (1,):
-        assert np.array_equal(res[0][0], res[form][0]), form
-        assert np.array_equal(res[0][1], res[form][1]), form
-        assert np.array_equal(res[0][2], res[form][2]), (form, res[0][2], res[form][2])
-    assert res[0][2][ads.STAT_DIMS] < res[0][2][ads.STAT_DCOS] * w.D
+    a, b = res[1], res[1 << 30]
+    assert np.array_equal(a[0], b[0])
+    assert np.array_equal(a[1], b[1])
+    assert np.array_equal(a[2], b[2]), (a[2], b[2])
+    assert a[2][ads.STAT_DIMS] < a[2][ads.STAT_DCOS] * w.D
+    if storage == 0:
+        ids, _, stats, probes = a
+        pr, _ = _check_probes(w, probes, nprobe)
+        _, gt = w.gt(K)
+        o_ids, _, o_st = w.oracle_search(pr, K, eps0, dd, method=method)
+        r_gpu = oracle.recall(ids, w.exact(ids), gt, K)
+        r_orc = oracle.recall(o_ids, w.exact(o_ids), gt, K)
+        assert abs(r_gpu - r_orc) <= 0.002 + 1.0 / (w.nq * K), (r_gpu, r_orc)
+        assert stats[ads.STAT_DCOS] == o_st[:, 0].sum()
 
 
 # ---------------------------------------------------------------------------

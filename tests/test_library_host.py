@@ -76,12 +76,12 @@ def test_calls_validate_before_launching(ads):
 
 def test_tuning_knobs_validate_and_round_trip(ads):
     saved = ads.get_tuning()
-    assert saved["dense_form"] == 0 and saved["dense_frac"] == 0.0
+    assert saved["prefetch_units"] == 0 and saved["dense_frac"] == 0.0
     try:
-        ads.set_tuning(dense_form=1, queries_per_unit=16, sweep_log2=2)
+        ads.set_tuning(prefetch_units=1, queries_per_unit=16, sweep_log2=2)
         t = ads.get_tuning()
-        assert (t["dense_form"], t["queries_per_unit"], t["sweep_log2"]) == (1, 16, 2)
-        for bad in ({"dense_form": 2}, {"dense_frac": 0.5}, {"dense_frac": -0.1}, {"queries_per_unit": 3},
+        assert (t["prefetch_units"], t["queries_per_unit"], t["sweep_log2"]) == (1, 16, 2)
+        for bad in ({"prefetch_units": -1}, {"dense_frac": 0.5}, {"dense_frac": -0.1}, {"queries_per_unit": 3},
                     {"sweep_log2": 7}, {"grid_per_xcd": -1}):
             with pytest.raises(ads.AdsError):
                 ads.set_tuning(**bad)
