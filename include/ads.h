@@ -57,7 +57,7 @@ typedef enum {
 typedef enum {
     ADS_METRIC_L2 = 0,      /* Euclidean distance (the paper's setting) */
     ADS_METRIC_COSINE = 1   /* cosine: base vectors, centres and queries are normalised to unit
-                               length, then searched in L2 (Section 7: cosine search equals
+                               length, then searched in L2 (Section 8, extension (1): cosine search equals
                                Euclidean search on normalised vectors) */
 } ads_metric;
 
@@ -173,7 +173,7 @@ ads_status ads_index_free(ads_index *ix);
 /*
  * ads_dco_batch -- DCOs of one rotated query against explicit candidates with
  * a fixed threshold r (Definition 2.1; Algorithm 1; the fixed-threshold
- * protocol of Section 6.2.5).
+ * protocol of Section 6.2.6).
  *   q_rot     device [D] float32, already rotated (P q).
  *   cand      device [m] int64 base ids; m >= 0.
  *   r         threshold distance (not squared), >= 0, +INF allowed.
@@ -203,7 +203,7 @@ ads_status ads_dco_batch(const ads_index *ix, const float *q_rot, const int64_t 
 
 /*
  * ads_dco_batch_ip -- inner-product comparison <o, q> >= r for explicit
- * candidates, reduced to a DCO on unit vectors (Section 7, extension (1)):
+ * candidates, reduced to a DCO on unit vectors (Section 8, extension (1)):
  * <o,q> >= r  <=>  || o/|o| - q/|q| || <= sqrt(2 - 2 r / (|o| |q|)), decided by
  * Algorithm 1 (or FDScanning / PDScanning) with that per-candidate threshold.
  * Needs an index built with ADS_METRIC_COSINE (it keeps the raw norms).

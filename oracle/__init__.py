@@ -16,7 +16,7 @@ What it computes, each function citing the passage it follows:
   (Section 2.2.2);
 * :func:`dco_batch` -- Definition 2.1 by FDScanning, Algorithm 1
   (ADSampling) or PDScanning (Section 6.1) for a fixed threshold;
-* :func:`ip_dco_batch` / :func:`normalize` -- Section 7's reduction of cosine
+* :func:`ip_dco_batch` / :func:`normalize` -- Section 8's reduction (extension (1)) of cosine
   search and inner-product comparisons to DCOs on unit vectors;
 * :func:`ivf_search` -- the IVF scan with a KNN max-heap (Section 2.2.2), with
   ADSampling as its DCO (IVF+, Section 4).  IVF++ (Section 5.2) changes only the
@@ -75,7 +75,12 @@ def _load():
         return _lib
     if not os.path.exists(_SO):
         build()
-    lib = ctypes.CDLL(_SO)
+    _lib = bind(ctypes.CDLL(_SO))
+    return _lib
+
+
+def bind(lib):
+    """Declares the C functions' signatures on a loaded library and returns it."""
     dp = ctypes.POINTER(ctypes.c_double)
     i64p = ctypes.POINTER(ctypes.c_int64)
     i32p = ctypes.POINTER(ctypes.c_int32)
@@ -96,7 +101,6 @@ def _load():
                                    i32p, ctypes.c_int, i32p, ctypes.c_int, ctypes.c_double,
                                    ctypes.c_int, ctypes.c_int, i64p, dp, i64p, ctypes.c_int]
     lib.orc_ivf_search.restype = ctypes.c_int
-    _lib = lib
     return lib
 
 
@@ -266,7 +270,7 @@ def dco_batch(base_rot: np.ndarray, q_rot: np.ndarray, rows: np.ndarray, r: floa
 
 
 # ---------------------------------------------------------------------------
-# Section 7, extension (1): cosine similarity and inner product
+# Section 8, extension (1): cosine similarity and inner product
 # ---------------------------------------------------------------------------
 
 
@@ -280,7 +284,7 @@ def normalize(x: np.ndarray) -> np.ndarray:
 def ip_dco_batch(base_raw: np.ndarray, q_raw: np.ndarray, rows: np.ndarray, r: float,
                  P64: np.ndarray, eps0: float, delta_d: int, method: int = METHOD_ADS,
                  band_rel: float = 1e-5):
-    """<o, q> >= r decided as a DCO on unit vectors (Section 7): the
+    """<o, q> >= r decided as a DCO on unit vectors (Section 8, extension (1)): the
     comparison holds iff || o/|o| - q/|q| || <= sqrt(2 - 2 r / (|o| |q|)).
 
     Returns dict(mask, ip (<o,q> for positives, -inf otherwise), dims, band)."""

@@ -22,7 +22,7 @@ __global__ __launch_bounds__(ADS_WG) void dco_kernel(
     if (i < m && ip) {
         const int64_t id = cand[i];
         if (id >= 0 && id < n) {
-            // <o,q> >= r  <=>  |o/|o| - q/|q||^2 <= 2 - 2 r / (|o||q|)   (Section 7)
+            // <o,q> >= r  <=>  |o/|o| - q/|q||^2 <= 2 - 2 r / (|o||q|)   (Section 8, extension (1))
             nn = ipa.onorm[id] * (*ipa.qnorm);
             r2 = nn > 0.f ? 2.f - 2.f * ipa.r_ip / nn : (ipa.r_ip <= 0.f ? __builtin_inff() : -1.f);
         }

@@ -114,6 +114,20 @@ def test_pds_golden_cases(case):
     assert math.isinf(res["dist"][0]) == (ex["dist"] == "inf")
 
 
+@pytest.mark.parametrize("case", _golden()["band"], ids=lambda c: c["name"])
+def test_band_golden_cases(case):
+    """The parity band (a decision taken within 1e-5 relative of its test
+    boundary): hand-derived cases just inside and just outside the boundary of
+    the Section 3.2 test, at the exact compare of Case 3, and for PDScanning."""
+    res = oracle.dco_batch(np.array([case["o"]], float), np.array(case["q"], float),
+                           np.array([0]), _f(case["r"]), _f(case["eps0"]), case["delta_d"],
+                           method=case["method"])
+    ex = case["expect"]
+    assert res["band"][0] == ex["band"]
+    assert res["mask"][0] == ex["positive"]
+    assert res["dims"][0] == ex["dims"]
+
+
 # --------------------------------------------------------------------------
 # Closed forms and invariants of Algorithm 1
 # --------------------------------------------------------------------------
@@ -269,7 +283,7 @@ def test_sequential_failure_rate_matches_gaussian_monte_carlo():
 
 def test_failure_rate_decreases_with_eps0_like_figure_12():
     """Fixed threshold = exact K-th NN distance, linear scan, delta_d = 1
-    (the verification protocol of Section 6.2.5): the recall of positives
+    (the verification protocol of Section 6.2.6): the recall of positives
     rises towards 1 as eps0 grows and is near 1 by eps0 = 2."""
     w = sd.WORKLOADS["flat_d128"]
     x = sd.base_vectors(w)[:3000]
@@ -327,6 +341,17 @@ def test_ivf_golden_tiny():
                                              method=method)
             assert ids[0].tolist() == case["ids"]
             assert np.allclose(dist[0], case["dist"], rtol=1e-12)
+
+
+def test_probe_selection_golden_ties():
+    """Probe order with exact ties at the boundary: ascending distance, then
+    the lower list id."""
+    with open(os.path.join(GOLDEN, "ivf_tiny.json")) as fh:
+        g = json.load(fh)["probe_cases"]
+    cent = np.array(g["centroids"], float)
+    for case in g["cases"]:
+        pr, _ = oracle.probes(np.array([case["q"]], float), cent, case["nprobe"])
+        assert pr[0].tolist() == case["probes"], case["why"]
 
 
 @pytest.mark.parametrize("method", [oracle.METHOD_FDS, oracle.METHOD_ADS])
@@ -390,7 +415,7 @@ def test_recall_and_ratio_metrics_hand_cases():
 
 
 # --------------------------------------------------------------------------
-# Section 7: cosine similarity and inner product
+# Section 8, extension (1): cosine similarity and inner product
 # --------------------------------------------------------------------------
 
 def test_inner_product_reduction_matches_direct_comparison():
@@ -416,7 +441,7 @@ def test_inner_product_reduction_matches_direct_comparison():
 
 def test_cosine_search_is_euclidean_search_on_unit_vectors():
     """Cosine search (largest cosine first) equals the Euclidean KNN of the
-    normalised vectors (Section 7)."""
+    normalised vectors (Section 8, extension (1))."""
     x = sd.lowrank(3000, 32, 61, 62, latent=8, noise=0.3)
     q = sd.lowrank(5, 32, 63, 62, latent=8, noise=0.3)
     xu, qu = oracle.normalize(x), oracle.normalize(q)
