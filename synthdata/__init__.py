@@ -226,7 +226,7 @@ WORKLOADS = {
     "ivf_d960": Workload("ivf_d960", "lowrank", n=1_000_000, nq=1_000, D=960, nlist=4096,
                          p_seed=1001, base_seed=1022, query_seed=1023,
                          kmeans_seed=1024, model_seed=1025, latent=64, noise=0.1,
-                         K=10, nprobe=64),
+                         K=10, nprobe=768, delta_d=16),
     "batched_d256": Workload("batched_d256", "lowrank", n=2_000_000, nq=4_096, D=256,
                              nlist=8192, p_seed=1001, base_seed=1032, query_seed=1033,
                              kmeans_seed=1034, model_seed=1035, draw_seed=1036,

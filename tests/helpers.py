@@ -77,3 +77,42 @@ def tie_band_equal(ids_a, d_a, ids_b, d_b, rel=1e-5):
     if sa != sb:
         return False
     return bool(np.all(np.abs(d_a[:len(ka)] - d_b[:len(kb)]) <= rel * np.maximum(d_b[:len(kb)], 1e-30)))
+
+
+def probe_band(q_rot: np.ndarray, c_rot: np.ndarray, d2: np.ndarray) -> np.ndarray:
+    """Per-centre rounding band (absolute, on squared distance) of the GPU's
+    probe keys against the FP64 oracle's, for one query.
+
+    The GPU rotates q and the centres in FP32 (each rotated vector is off by
+    about sqrt(D) u |x| in norm, u = 2^-24, for rounding errors of random
+    sign), which moves a squared distance by up to 2 dis (|dq| + |dc|); it then
+    scores in the GEMM form |q|^2 + |c|^2 - 2 q.c with FP32 sums of D terms,
+    whose rounding is about sqrt(D) u (|q| + |c|)^2.  The band is four times
+    the sum of both (four standard deviations).
+    """
+    D = q_rot.shape[0]
+    u = 2.0 ** -24
+    qn = float(np.linalg.norm(q_rot))
+    cn = np.linalg.norm(c_rot, axis=1)
+    s = qn + cn
+    return 4.0 * math.sqrt(D) * u * (s * s + 2.0 * np.sqrt(np.maximum(d2, 0.0)) * s)
+
+
+def probes_agree(probes_gpu: np.ndarray, probes_orc: np.ndarray, q_rot: np.ndarray,
+                 c_rot: np.ndarray, d2: np.ndarray) -> bool:
+    """Checks one query's probe list against the oracle's.  Returns True when
+    they are identical; otherwise asserts that every centre in one list but not
+    the other lies within the rounding band of the oracle's nprobe-th squared
+    distance (both bands added), and returns False."""
+    g = [int(v) for v in probes_gpu if v >= 0]
+    o = [int(v) for v in probes_orc if v >= 0]
+    if g == o:
+        return True
+    band = probe_band(q_rot, c_rot, d2)
+    kth_id = o[-1]
+    kth = d2[kth_id]
+    near = np.abs(d2 - kth) <= band + band[kth_id]
+    diff = set(g) ^ set(o)
+    outside = [j for j in diff if not near[j]]
+    assert not outside, f"probe lists differ outside the rounding band: {outside[:5]}"
+    return False

@@ -16,7 +16,7 @@ import pytest
 
 import oracle
 import synthdata as sd
-from helpers import tie_band_equal
+from helpers import probes_agree, tie_band_equal
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -54,14 +54,17 @@ class Full:
 
     _xr = None
 
-    def oracle_on_sample(self, probes_s, K, eps0, method, nprobe=None):
-        """IVF scan of the sampled queries by the oracle (FP64 rotation of
-        every base row, done once)."""
+    def xr(self):
+        """FP64 rotation of every base row (done once)."""
         if self._xr is None:
             self._xr = np.empty((self.w.n, self.w.D))
             for s in range(0, self.w.n, 65536):
                 self._xr[s:s + 65536] = oracle.rotate(self.x[s:s + 65536], self.P64)
-        return oracle.ivf_search(self._xr, self.qr_s, self.off, self.members, probes_s, K, eps0,
+        return self._xr
+
+    def oracle_on_sample(self, probes_s, K, eps0, method, nprobe=None):
+        """IVF scan of the sampled queries by the oracle."""
+        return oracle.ivf_search(self.xr(), self.qr_s, self.off, self.members, probes_s, K, eps0,
                                  self.w.delta_d, method=method, nprobe=nprobe)
 
     def exact(self, ids, qidx):
@@ -99,13 +102,7 @@ def _check_sample(F, ids, dist, probes, K, eps0, method, npq=None):
         n_i = probes.shape[1] if npq is None else int(npq[i])
         gp = probes[r][:n_i]
         op = pr_o[r][:n_i]
-        if list(gp) == list(op):
-            same.append(True)
-            continue
-        kth = d2[r][op[-1]]
-        band = set(np.flatnonzero(np.abs(d2[r] - kth) <= 1e-4 * kth).tolist())
-        assert set(gp) - band == set(op) - band, f"query {i}: probe sets differ outside the band"
-        same.append(False)
+        same.append(probes_agree(gp, op, F.qr_s[r], F.cr, d2[r]))
     probes_s = np.where(np.arange(probes.shape[1])[None, :] < (
         probes.shape[1] if npq is None else npq[s][:, None]), probes, -1).astype(np.int32)
     # the oracle scans the GPU's probe order only when it equals its own
@@ -115,7 +112,13 @@ def _check_sample(F, ids, dist, probes, K, eps0, method, npq=None):
 
 
 def test_d960_at_bench_operating_point(ads):
+    """The benchmark's own configuration: ivf_d960 with delta_d 16, nprobe 768,
+    K = 10, eps0 = 2.1, float32 storage, all 1,000 queries in one batch.  The
+    recall of the GPU search equals the recall of the oracle's sequential IVF+
+    on every query within 0.002 (Corollary 4.2: both keep the exact scan's
+    result with high probability)."""
     F = Full(ads, "ivf_d960")
+    assert F.w.delta_d == 16
     nprobe, K = 768, 10
     stats = torch.zeros(ads.NSTATS, dtype=torch.int64, device="cuda")
     ids, dist, probes = ads.search(F.ix, F.qd, K, nprobe, eps0=2.1, want_probes=True, stats=stats)
@@ -132,14 +135,21 @@ def test_d960_at_bench_operating_point(ads):
     for r in range(SAMPLE):
         if same[r]:
             assert tie_band_equal(f_ids[r], f_dist[r], o_ids[r], o_d[r]), r
-    # ADSampling recall on the sample within the parity bar of the oracle's
-    _, gt = oracle.brute_knn(F.x, F.q[F.sample], K)
-    a_ids = ids[F.sample]
-    oa_ids, oa_d, _, _, _ = _check_sample(F, a_ids, dist[F.sample], probes[F.sample], K, 2.1,
-                                          oracle.METHOD_ADS)
-    r_gpu = oracle.recall(a_ids, F.exact(a_ids, F.sample), gt, K)
-    r_orc = oracle.recall(oa_ids, F.exact(oa_ids, F.sample), gt, K)
-    assert abs(r_gpu - r_orc) <= 0.002 + 1.0 / (SAMPLE * K)
+    # ADSampling: the oracle's sequential IVF+ on every query, its own probes
+    nq = F.w.nq
+    qr = oracle.rotate(F.q, F.P64)
+    pr_o, d2 = oracle.probes(qr, F.cr, nprobe)
+    differ = sum(not probes_agree(probes[i], pr_o[i], qr[i], F.cr, d2[i]) for i in range(nq))
+    assert differ <= nq // 20
+    oa_ids, _, oa_st = oracle.ivf_search(F.xr(), qr, F.off, F.members, pr_o, K, 2.1, F.w.delta_d)
+    _, gt = oracle.brute_knn(F.x, F.q, K)
+    r_gpu = oracle.recall(ids, F.exact(ids, np.arange(nq)), gt, K)
+    r_orc = oracle.recall(oa_ids, F.exact(oa_ids, np.arange(nq)), gt, K)
+    print(f"ivf_d960 nprobe {nprobe}: recall gpu {r_gpu:.4f} oracle {r_orc:.4f}; dims ratio gpu "
+          f"{st[ads.STAT_DIMS] / (st[ads.STAT_DCOS] * F.w.D):.4f} oracle "
+          f"{oracle.dims_ratio(oa_st, F.w.D):.4f}; probe lists differing {differ}")
+    assert r_gpu >= 0.95
+    assert abs(r_gpu - r_orc) <= 0.002, (r_gpu, r_orc)
     F.ix.free()
 
 
