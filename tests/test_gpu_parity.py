@@ -255,7 +255,8 @@ def test_search_with_more_lists_than_one_xcd_range_sorts(ads):
     # many centres are nearly equidistant here: the probe lists must agree
     # outside the rounding band; queries whose lists agree exactly are compared
     pr, nbad = _check_probes(w, probes, nprobe)
-    same = [i for i in range(w.nq) if list(probes[i]) == list(pr[i])]
+    # FDScanning's result depends on the probed set, not on the probe order
+    same = [i for i in range(w.nq) if set(probes[i].tolist()) == set(pr[i].tolist())]
     assert len(same) >= w.nq // 2, nbad
     o_ids, o_d, _ = w.oracle_search(pr, K, math.inf, 16, method=oracle.METHOD_FDS)
     for i in same:
