@@ -60,9 +60,16 @@ def parse():
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fds", action="store_true")
-    ap.add_argument("--mode", default="search", choices=["search", "serve"],
+    ap.add_argument("--no-pds", action="store_true",
+                    help="skip the PDScanning leg (IVF** on an unrotated index)")
+    ap.add_argument("--mode", default="search", choices=["search", "serve", "verify"],
                     help="search: the throughput benchmark (default); serve: the continuous-"
-                         "batching request loop at Poisson arrival rates")
+                         "batching request loop at Poisson arrival rates; verify: the fixed-"
+                         "threshold failure-rate / dims sweep over eps0 and the linear-scan "
+                         "feasibility run")
+    ap.add_argument("--verify-queries", type=int, default=20, help="verify mode: queries")
+    ap.add_argument("--verify-n", type=int, default=200_000,
+                    help="verify mode: base vectors of the linear scans (the first n of the workload)")
     ap.add_argument("--rates", default="5000,20000,50000", help="serve mode: arrivals per second")
     ap.add_argument("--serve-requests", type=int, default=20000, help="serve mode: requests per rate")
     ap.add_argument("--serve-nprobe", default="32,64",
@@ -146,8 +153,9 @@ def main() -> int:
         del src, dst
         log("calibration copy: 1 GiB read + 1 GiB written")
 
-    def run(nprobe, eps0, stats=None):
-        ids, dist = ads.search(ix, qd, K, nprobe, eps0=eps0, rerank=rerank, stats=stats)
+    def run(nprobe, eps0, stats=None, index=None, method=ads.ADSAMPLING):
+        ids, dist = ads.search(index or ix, qd, K, nprobe, eps0=eps0, rerank=rerank, stats=stats,
+                               method=method)
         return ids, dist
 
     last_ids = {}
@@ -175,11 +183,11 @@ def main() -> int:
                 break
         return best
 
-    def timed(nprobe, eps0, label):
+    def timed(nprobe, eps0, label, **kw):
         for _ in range(args.warmup):
-            run(nprobe, eps0)
+            run(nprobe, eps0, **kw)
         stats = torch.zeros(ads.NSTATS, dtype=torch.int64, device="cuda")
-        run(nprobe, eps0, stats)
+        run(nprobe, eps0, stats, **kw)
         torch.cuda.synchronize()
         st = stats.cpu().numpy()
         ads.profile_enable(True)
@@ -187,7 +195,7 @@ def main() -> int:
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(args.steps):
-            run(nprobe, eps0)
+            run(nprobe, eps0, **kw)
         torch.cuda.synchronize()
         el = time.perf_counter() - t
         ads.profile_enable(False)
@@ -199,6 +207,9 @@ def main() -> int:
 
     if args.mode == "serve":
         return serve(args, w, ix, q, gt, x)
+    if args.mode == "verify":
+        ix.free()
+        return verify(args, w, x, q, G)
 
     p_ads, r_ads = operating_point(args.eps0, "ADSampling")
     ids_ads = last_ids[args.eps0]
@@ -211,6 +222,26 @@ def main() -> int:
                "qps": round(w.nq / (ms_fds / 1e3), 1),
                "dcos_per_s": round(float(st_fds[ads.STAT_DCOS]) / (ms_fds / 1e3), 1),
                "scan_ms_per_step": round(ph_fds["scan"][0] / args.steps, 4)}
+
+    pds = None
+    if not args.no_pds and storage == ads.F32:
+        # IVF** (Section 6.1): PDScanning on the original coordinates, same lists,
+        # an index built without the rotation, at the ADSampling operating point
+        ix_raw = ads.ivf_build(x, None, cent, assign, delta_d=args.delta_d, storage=ads.F32,
+                               keep_fp32=False)
+        torch.cuda.synchronize()
+        p_ids, _ = run(p_ads, math.inf, index=ix_raw, method=ads.PDSCANNING)
+        torch.cuda.synchronize()
+        p_ids = p_ids.cpu().numpy()
+        r_pds = oracle.recall(p_ids, exact_for(x, q, p_ids), gt, K)
+        ms_pds, st_pds, ph_pds = timed(p_ads, math.inf, "PDScanning (unrotated)", index=ix_raw,
+                                       method=ads.PDSCANNING)
+        pds = {"nprobe": p_ads, "recall": round(r_pds, 4), "ms_per_step": round(ms_pds, 4),
+               "qps": round(w.nq / (ms_pds / 1e3), 1),
+               "dims_ratio": round(float(st_pds[ads.STAT_DIMS]) / max(1.0, float(st_pds[ads.STAT_DCOS]) * w.D), 5),
+               "dcos_per_s": round(float(st_pds[ads.STAT_DCOS]) / (ms_pds / 1e3), 1),
+               "scan_ms_per_step": round(ph_pds["scan"][0] / args.steps, 4)}
+        ix_raw.free()
 
     qps = w.nq / (ms_ads / 1e3)
     dcos = float(st_ads[ads.STAT_DCOS])
@@ -253,6 +284,8 @@ def main() -> int:
         "dims_ratio": round(dims / max(1.0, dcos * w.D), 5),
         "speedup_vs_fdscanning": round(fds["ms_per_step"] / ms_ads, 3) if fds else None,
         "fdscanning": fds,
+        "pdscanning_unrotated": pds,
+        "speedup_vs_pdscanning": round(pds["ms_per_step"] / ms_ads, 3) if pds else None,
         "phase_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in ph_ads.items()},
         "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3),
                      "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -310,6 +343,82 @@ def serve(args, w, ix, q, gt, x):
             "rates": out}
     print(json.dumps(line), flush=True)
     ix.free()
+    return 0
+
+
+def verify(args, w, x, q, G):
+    """Section 6.2.6: a linear scan with the threshold fixed at the exact K-th
+    NN distance, delta_d = 1, eps0 from 0 to 4: failure rate (true neighbours
+    rejected) and evaluated dims.  Section 6.2.4 (Fig. 8 methodology): an exact
+    KNN by linear scan (one list, sequential thresholds) with ADSampling DCOs,
+    recall and evaluated dims per eps0 at delta_d 8 and 32."""
+    import torch
+
+    import oracle
+    import paper_2303_09855_amd as ads
+    n = min(args.verify_n, w.n)
+    nq = min(args.verify_queries, w.nq)
+    xs, qs = x[:n], q[:nq]
+    K = args.K
+    _, gt = oracle.brute_knn(xs, qs, K)
+    P32, _ = ads.make_rotation(G)
+    qrot = ads.rotate(P32, qs)
+    eps_grid = [0.0, 0.5, 1.0, 1.5, 2.0, 2.5, 3.0, 3.5, 4.0]
+    fixed = []
+    ix = ads.ivf_build(xs, P32, xs.mean(axis=0, keepdims=True), np.zeros(n, dtype=np.int32),
+                       delta_d=32 if w.D % 32 == 0 else 8, storage=ads.F32, keep_fp32=True)
+    cand = torch.arange(n, dtype=torch.int64, device="cuda")
+    for eps0 in eps_grid:
+        fails = pos = 0
+        dims = 0
+        for i in range(nq):
+            r = float(gt[i, K - 1])
+            mask, _, dd = ads.dco_batch(ix, qrot[i], cand, r, eps0, 1)
+            torch.cuda.synchronize()
+            m = mask.cpu().numpy()
+            raw = oracle.exact_dist(xs, qs[i])
+            # true neighbours strictly inside r (objects tied with the K-th sit on the boundary)
+            tp = raw < r * (1 - 1e-6)
+            pos += int(tp.sum())
+            fails += int(np.sum(tp & (m == 0)))
+            dims += int(dd.sum().item())
+        row = {"eps0": eps0, "failure_rate": round(fails / max(1, pos), 6),
+               "dims_frac": round(dims / (n * nq * w.D), 5)}
+        log(f"verify fixed r: eps0 {eps0}: failure rate {row['failure_rate']:.5f}, dims {row['dims_frac']:.4f}")
+        fixed.append(row)
+    ix.free()
+    scans = []
+    for dd_layout in (8, 32):
+        if w.D % dd_layout:
+            continue
+        ixf = ads.ivf_build(xs, P32, xs.mean(axis=0, keepdims=True), np.zeros(n, dtype=np.int32),
+                            delta_d=dd_layout, storage=ads.F32, keep_fp32=False)
+        for eps0 in eps_grid[1:] + [math.inf]:
+            st = torch.zeros(ads.NSTATS, dtype=torch.int64, device="cuda")
+            ids, _ = ads.search(ixf, qs, K, 1, eps0=eps0, stats=st)
+            torch.cuda.synchronize()
+            ids = ids.cpu().numpy()
+            stv = st.cpu().numpy()
+            rec = oracle.recall(ids, exact_for(xs, qs, ids), gt, K)
+            row = {"delta_d": dd_layout, "eps0": eps0 if math.isfinite(eps0) else "inf",
+                   "recall": round(rec, 5),
+                   "dims_ratio": round(float(stv[ads.STAT_DIMS]) / max(1.0, float(stv[ads.STAT_DCOS]) * w.D), 5)}
+            log(f"verify linear scan: delta_d {dd_layout} eps0 {eps0}: recall {rec:.4f}, dims {row['dims_ratio']:.4f}")
+            scans.append(row)
+        ixf.free()
+    best = {}
+    for row in scans:
+        if row["recall"] >= 0.999 and row["eps0"] != "inf":
+            b = best.get(row["delta_d"])
+            if b is None or row["dims_ratio"] < b["dims_ratio"]:
+                best[row["delta_d"]] = row
+    line = {"metric": "fixed-threshold failure rate and evaluated dims vs eps0; linear-scan dims at recall > 0.999",
+            "value": fixed[4]["failure_rate"], "unit": "failure rate at eps0 = 2", "n_gpus": 1,
+            "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"{w.name}: first {n} base vectors, {nq} queries, K={K}, D={w.D}"},
+            "fixed_threshold_delta_d_1": fixed, "linear_scan": scans,
+            "linear_scan_best_at_recall_0_999": best}
+    print(json.dumps(line), flush=True)
     return 0
 
 

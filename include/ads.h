@@ -76,6 +76,7 @@ typedef struct {
     int32_t max_list;       /* largest list size */
     int32_t metric;         /* ads_metric */
     int64_t device_bytes;   /* device memory held by the index */
+    int32_t rotated;        /* 1 if built with a rotation P, 0 for unrotated vectors */
 } ads_index_desc;
 
 /* Counters accumulated by ads_search / ads_dco_batch into a caller buffer of
@@ -125,7 +126,12 @@ ads_status ads_rotate(const float *P, int32_t D, const float *X, int64_t n, floa
  * caller (in the paper the k-means clustering comes from an external library,
  * Section 6.1; the index is the same for IVF, IVF+ and IVF++).
  *   base       device [n][D] float32 raw vectors; n >= 1.
- *   P          device [D][D] float32 rotation (copied into the index).
+ *   P          device [D][D] float32 rotation (copied into the index), or NULL
+ *              for an index of the unrotated vectors: the layout of IVF** and
+ *              the baseline IVF* of Section 6.1 (PDScanning on the original
+ *              coordinates).  Such an index accepts FDScanning and PDScanning
+ *              and rejects ADSampling with a finite eps0 (ADS_EINVAL): the test
+ *              of Section 3.2 relies on the random rotation.
  *   centroids  device [nlist][D] float32 raw-space list centres.
  *   assign     device [n] int32 list id of every vector, in [0, nlist).
  *   delta_d    block width of the stored layout: D % delta_d == 0 and
@@ -151,6 +157,44 @@ ads_status ads_ivf_build(const float *base, int64_t n, int32_t D, const float *P
                          int32_t delta_d, int32_t storage, int32_t keep_fp32, int32_t metric,
                          hipStream_t stream, ads_index **out);
 
+/*
+ * ads_kmeans -- Lloyd's k-means clustering of the index phase (Section 2.2.2:
+ * IVF partitions the data into the clusters of k-means; Section 6.1 runs it
+ * with a library and 4,096 clusters), on the GPU, trained on all n rows.
+ *   x          device [n][D] float32 rows; n >= 1, 1 <= D <= 4096.
+ *   nlist      number of clusters, 1 <= nlist <= n.
+ *   iters      Lloyd iterations, >= 0 (0: the seeded rows are the centres).
+ *   seed       initialisation: row i draws the SplitMix64 output of the
+ *              counter seed + (i + 1) * 0x9E3779B97F4A7C15 (Steele, Lea and
+ *              Flood, 2014); the nlist rows with the smallest draws, in
+ *              ascending draw order, are the initial centres 0..nlist-1.
+ *   centroids  device [nlist][D] float32 out: final centres.
+ *   assign     device [n] int32 out: list of every row under the final centres.
+ * One iteration assigns every row to its nearest centre (squared distance in
+ * the FP32 form |x|^2 + |c|^2 - 2 x.c, products on the matrix cores; ties to
+ * the lower centre id), then hands every empty list, in ascending id order,
+ * the member of the currently largest list (lower id on ties) farthest from
+ * its centre (lower row on ties), then moves every centre to the mean of its
+ * members (float64 sums in ascending row order, rounded once to float32).  A
+ * final assignment to the final centres gives `assign`.  Deterministic.
+ * Allocates device workspace (about 256 MB of centre products plus O(n)).
+ * Synchronises the stream.  Errors: ADS_EINVAL, ADS_ENOMEM, ADS_EHIP.
+ */
+ads_status ads_kmeans(const float *x, int64_t n, int32_t D, int32_t nlist, int32_t iters, uint64_t seed,
+                      float *centroids, int32_t *assign, hipStream_t stream);
+
+/*
+ * ads_build_ivf -- the whole index phase: ads_kmeans on the base vectors
+ * (on the unit-normalised vectors for ADS_METRIC_COSINE), then ads_ivf_build
+ * with the resulting centres and lists.  Arguments as those two calls;
+ * centroids_out ([nlist][D]) and assign_out ([n]) are device buffers that
+ * receive the clustering, or NULL (the library then uses its own).
+ */
+ads_status ads_build_ivf(const float *base, int64_t n, int32_t D, const float *P, int32_t nlist,
+                         int32_t iters, uint64_t seed, int32_t delta_d, int32_t storage, int32_t keep_fp32,
+                         int32_t metric, float *centroids_out, int32_t *assign_out, hipStream_t stream,
+                         ads_index **out);
+
 /* ads_index_info -- HOST: fills *info (host pointer).  ADS_EINVAL on NULL. */
 ads_status ads_index_info(const ads_index *ix, ads_index_desc *info);
 
@@ -174,13 +218,15 @@ ads_status ads_index_free(ads_index *ix);
  * ads_dco_batch -- DCOs of one rotated query against explicit candidates with
  * a fixed threshold r (Definition 2.1; Algorithm 1; the fixed-threshold
  * protocol of Section 6.2.6).
- *   q_rot     device [D] float32, already rotated (P q).
+ *   q_rot     device [D] float32, already rotated (P q); the raw query for an
+ *             index built without P.
  *   cand      device [m] int64 base ids; m >= 0.
  *   r         threshold distance (not squared), >= 0, +INF allowed.
  *   eps0      test parameter epsilon_0 >= 0 (Section 3.2); +INF never rejects.
  *   delta_d   coordinates sampled per step, 1 <= delta_d <= D (any value; the
  *             last step may be shorter).
- *   method    ads_method.  PDScanning here runs on the rotated coordinates.
+ *   method    ads_method.  PDScanning runs on the coordinates the index stores
+ *             (rotated, or original for an index built without P).
  *   source    0: read the blocked list layout; 1: read the float32 row copy
  *             (index built with keep_fp32).  Both give identical decisions for
  *             float32 storage (the IVF+ == IVF++ property of Section 5.2).
@@ -232,7 +278,10 @@ ads_status ads_dco_batch_ip(const ads_index *ix, const float *q, const int64_t *
  *   k_max     >= 1; nprobe_max in [1, nlist] and at most 4096 (above:
  *             ADS_EUNSUPPORTED).
  *   eps0      >= 0, +INF selects FDScanning (no statistical test).
- *   method    ads_method (PDScanning compares partial rotated distances).
+ *   method    ads_method.  PDScanning compares partial distances over the
+ *             coordinates the index stores: on an index built without P it is
+ *             the paper's IVF* / IVF** baseline (Section 6.1); queries are then
+ *             not rotated.
  *   rerank    0: plain search.  1: low-precision mode: scan with a KNN set of
  *             4K, then recompute the 4K survivors' distances from the float32
  *             row copy and return the best K (index built with keep_fp32).
@@ -260,6 +309,26 @@ ads_status ads_search(const ads_index *ix, const float *q, int32_t nq, const int
  * method and eps0 (0 on invalid arguments, with ads_last_error set). */
 uint64_t ads_search_workspace_size(const ads_index *ix, int32_t nq, int32_t k_max,
                                    int32_t nprobe_max, int32_t rerank);
+
+/*
+ * ads_search_noalloc -- ads_search for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments and results as ads_search without the
+ * workspace argument: the workspace is a file-scope device array of
+ * ADS_NOALLOC_SCRATCH_BYTES bytes inside the library (each GPU the library
+ * runs on holds its own copy until the process ends).  Calls no allocating
+ * routine.  Sizes whose workspace (ads_search_workspace_size) exceeds the
+ * array are rejected with ADS_EINVAL and a message.  All calls on one GPU
+ * share that GPU's array: calls that overlap on one GPU (different streams
+ * or threads without ordering between them) race and must be serialised by
+ * the caller.  The first call on a device looks up the array's device
+ * address with that device current.
+ */
+#define ADS_NOALLOC_SCRATCH_BYTES (256ull << 20)
+ads_status ads_search_noalloc(const ads_index *ix, const float *q, int32_t nq, const int32_t *K,
+                              const int32_t *nprobe, int32_t k_max, int32_t nprobe_max, float eps0,
+                              int32_t method, int32_t rerank, int64_t *ids, float *dist,
+                              int32_t *probes_out, int64_t *stats, hipStream_t stream);
 
 /* --------------------------------------------------------------------------
  * Captured searches: one graph launch per batch.

@@ -18,6 +18,8 @@ What it computes, each function citing the passage it follows:
   (ADSampling) or PDScanning (Section 6.1) for a fixed threshold;
 * :func:`ip_dco_batch` / :func:`normalize` -- Section 8's reduction (extension (1)) of cosine
   search and inner-product comparisons to DCOs on unit vectors;
+* :func:`kmeans` -- the k-means clustering of the IVF index phase (Section 2.2.2,
+  Section 6.1), seeded by :func:`kmeans_init_rows` (SplitMix64 counters);
 * :func:`ivf_search` -- the IVF scan with a KNN max-heap (Section 2.2.2), with
   ADSampling as its DCO (IVF+, Section 4).  IVF++ (Section 5.2) changes only the
   memory layout and gives the same result, so one oracle covers both;
@@ -377,6 +379,82 @@ def ivf_search(base_rot: np.ndarray, q_rot: np.ndarray, list_off: np.ndarray,
     if rc != 0:
         raise MemoryError("oracle ivf_search failed to allocate")
     return out_ids, out_dist, stats
+
+
+# ---------------------------------------------------------------------------
+# Section 2.2.2 (index phase): k-means clustering into the inverted lists
+# ---------------------------------------------------------------------------
+
+_MASK64 = (1 << 64) - 1
+_GOLDEN64 = 0x9E3779B97F4A7C15
+
+
+def splitmix64(x: int) -> int:
+    """The SplitMix64 output function (Steele, Lea and Flood, OOPSLA 2014) of a
+    64-bit state value."""
+    z = x & _MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+    return z ^ (z >> 31)
+
+
+def kmeans_init_rows(n: int, nlist: int, seed: int) -> np.ndarray:
+    """The nlist distinct rows of the seeded initialisation: row i draws the
+    SplitMix64 value of the counter seed + (i + 1) * golden gamma; the rows with
+    the nlist smallest values, in ascending value order, seed lists 0..nlist-1."""
+    keys = [splitmix64((seed + (i + 1) * _GOLDEN64) & _MASK64) for i in range(n)]
+    return np.array(sorted(range(n), key=lambda i: keys[i])[:nlist], dtype=np.int64)
+
+
+def _nearest(x: np.ndarray, c: np.ndarray):
+    """Nearest centre of every row (difference form, ties to the lower id) and
+    the squared distance to it."""
+    lab = np.empty(x.shape[0], dtype=np.int64)
+    d2 = np.empty(x.shape[0])
+    for i in range(x.shape[0]):
+        diff = c - x[i][None, :]
+        dd = np.einsum("ij,ij->i", diff, diff)
+        j = int(np.argmin(dd))          # first minimum: the lower id on ties
+        lab[i] = j
+        d2[i] = dd[j]
+    return lab, d2
+
+
+def kmeans(x: np.ndarray, nlist: int, iters: int, seed: int = 0, init=None):
+    """Lloyd's k-means in float64 (the IVF index phase clusters the data with
+    k-means, Section 2.2.2; Section 6.1).  Readings where the paper is silent:
+    the seeded initial rows of kmeans_init_rows; every iteration assigns each
+    row to its nearest centre (ties to the lower id), then gives every empty
+    list, in ascending id order, the member of the currently largest list
+    (lower id on ties) that lies farthest from its centre (lower row on ties),
+    then moves every centre to the mean of its members; a final assignment to
+    the final centres gives the lists.
+
+    ``init`` (row indices) replaces the seeded initial rows when given.
+
+    Returns (centres [nlist, D] float64, assignment [n] int64)."""
+    xd = np.asarray(x, dtype=np.float64)
+    n = xd.shape[0]
+    if init is None:
+        init = kmeans_init_rows(n, nlist, seed)
+    init = np.asarray(init, dtype=np.int64)
+    c = xd[init].copy()
+    for _ in range(iters):
+        lab, d2 = _nearest(xd, c)
+        counts = np.bincount(lab, minlength=nlist)
+        for j in range(nlist):
+            if counts[j] > 0:
+                continue
+            big = int(np.argmax(counts))            # first maximum: the lower id
+            members = np.flatnonzero(lab == big)
+            far = members[np.argmax(d2[members])]   # first maximum: the lower row
+            lab[far] = j
+            counts[big] -= 1
+            counts[j] = 1
+        for j in range(nlist):
+            c[j] = xd[lab == j].mean(axis=0)
+    lab, _ = _nearest(xd, c)
+    return c, lab
 
 
 # ---------------------------------------------------------------------------

@@ -8,6 +8,7 @@ used for device memory and streams only.
 from ._binding import (  # noqa: F401
     ADSAMPLING, BF16, EXPORTED, F16, F32, FDSCANNING, NSTATS, PDSCANNING, STAT_BYTES, STAT_DCOS,
     STAT_DIMS, STAT_POSITIVES, AdsError, Index, dco_batch, ivf_build, last_error, load,
-    make_rotation, profile_collect, profile_enable, rotate, search, search_workspace_size, version,
-    PHASES, METRIC_COSINE, METRIC_L2, Plan, dco_batch_ip, get_tuning, set_tuning,
+    make_rotation, profile_collect, profile_enable, rotate, search, search_noalloc, search_workspace_size, version,
+    PHASES, METRIC_COSINE, METRIC_L2, NOALLOC_SCRATCH_BYTES, Plan, dco_batch_ip, get_tuning, set_tuning,
+    build_ivf, kmeans,
 )

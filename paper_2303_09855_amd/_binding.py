@@ -26,8 +26,9 @@ EXPORTED = [
     "ads_index_free", "ads_dco_batch", "ads_search", "ads_search_workspace_size",
     "ads_last_error", "ads_version", "ads_profile_enable", "ads_profile_collect",
     "ads_set_tuning", "ads_get_tuning", "ads_plan_create", "ads_plan_launch", "ads_plan_free",
-    "ads_dco_batch_ip",
+    "ads_dco_batch_ip", "ads_search_noalloc", "ads_kmeans", "ads_build_ivf",
 ]
+NOALLOC_SCRATCH_BYTES = 256 << 20       # ADS_NOALLOC_SCRATCH_BYTES
 METRIC_L2, METRIC_COSINE = 0, 1
 PHASES = ["rotate", "probe", "group", "scan", "merge", "output"]
 
@@ -48,7 +49,8 @@ class IndexDesc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("D", ctypes.c_int32), ("nlist", ctypes.c_int32),
                 ("delta_d", ctypes.c_int32), ("storage", ctypes.c_int32),
                 ("has_fp32_copy", ctypes.c_int32), ("max_list", ctypes.c_int32),
-                ("metric", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
+                ("metric", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
+                ("rotated", ctypes.c_int32)]
 
 
 _lib = None
@@ -73,6 +75,10 @@ def load() -> ctypes.CDLL:
     lib.ads_index_free.argtypes = [vp]
     lib.ads_dco_batch.argtypes = [vp, vp, vp, i64, f32, f32, i32, i32, i32, vp, vp, vp, vp, vp]
     lib.ads_search.argtypes = [vp, vp, i32, vp, vp, i32, i32, f32, i32, i32, vp, vp, vp, vp, vp, vp]
+    lib.ads_kmeans.argtypes = [vp, i64, i32, i32, i32, ctypes.c_uint64, vp, vp, vp]
+    lib.ads_build_ivf.argtypes = [vp, i64, i32, vp, i32, i32, ctypes.c_uint64, i32, i32, i32, i32, vp, vp,
+                                  vp, ctypes.POINTER(vp)]
+    lib.ads_search_noalloc.argtypes = [vp, vp, i32, vp, vp, i32, i32, f32, i32, i32, vp, vp, vp, vp, vp]
     lib.ads_search_workspace_size.argtypes = [vp, i32, i32, i32, i32]
     lib.ads_search_workspace_size.restype = ctypes.c_uint64
     lib.ads_plan_create.argtypes = [vp, vp, i32, vp, vp, i32, i32, f32, i32, i32, vp, vp, vp, vp,
@@ -205,7 +211,7 @@ def ivf_build(base, P, centroids, assign, delta_d: int = 32, storage: int = F32,
               keep_fp32: bool = True, metric: int = METRIC_L2) -> Index:
     torch = _torch()
     base = _dev(base, torch.float32)
-    P = _dev(P, torch.float32)
+    P = _dev(P, torch.float32) if P is not None else None      # None: unrotated index
     centroids = _dev(centroids, torch.float32)
     assign = _dev(assign, torch.int32)
     n, D = base.shape
@@ -214,6 +220,40 @@ def ivf_build(base, P, centroids, assign, delta_d: int = 32, storage: int = F32,
                                 _ptr(assign), int(delta_d), int(storage), int(bool(keep_fp32)),
                                 int(metric), _stream(), ctypes.byref(out)))
     return Index(out)
+
+
+def kmeans(x, nlist: int, iters: int = 10, seed: int = 0):
+    """GPU k-means (ads_kmeans).  Returns (centroids [nlist, D] float32,
+    assignment [n] int32) as device tensors."""
+    torch = _torch()
+    x = _dev(x, torch.float32)
+    n, D = x.shape
+    cent = torch.empty((nlist, D), dtype=torch.float32, device="cuda")
+    assign = torch.empty(n, dtype=torch.int32, device="cuda")
+    _check(load().ads_kmeans(_ptr(x), n, D, int(nlist), int(iters), ctypes.c_uint64(seed), _ptr(cent),
+                             _ptr(assign), _stream()))
+    return cent, assign
+
+
+def build_ivf(base, P, nlist: int, iters: int = 10, seed: int = 0, delta_d: int = 32,
+              storage: int = F32, keep_fp32: bool = True, metric: int = METRIC_L2,
+              want_clustering: bool = False):
+    """Index phase on the GPU: k-means then the blocked layout (ads_build_ivf).
+    Returns the Index, or (Index, centroids, assignment) with want_clustering."""
+    torch = _torch()
+    base = _dev(base, torch.float32)
+    P = _dev(P, torch.float32) if P is not None else None
+    n, D = base.shape
+    cent = torch.empty((nlist, D), dtype=torch.float32, device="cuda") if want_clustering else None
+    assign = torch.empty(n, dtype=torch.int32, device="cuda") if want_clustering else None
+    out = ctypes.c_void_p()
+    _check(load().ads_build_ivf(_ptr(base), n, D, _ptr(P), int(nlist), int(iters), ctypes.c_uint64(seed),
+                                int(delta_d), int(storage), int(bool(keep_fp32)), int(metric), _ptr(cent),
+                                _ptr(assign), _stream(), ctypes.byref(out)))
+    ix = Index(out)
+    if want_clustering:
+        return ix, cent, assign
+    return ix
 
 
 # ---------------------------------------------------------------------------
@@ -279,6 +319,32 @@ def search(index: Index, q, k_max: int, nprobe_max: int, eps0: float = 2.1,
     _check(load().ads_search(index.handle, _ptr(q), nq, _ptr(Kt), _ptr(Nt), int(k_max),
                              int(nprobe_max), e, int(method), int(rerank), _ptr(ids), _ptr(dist),
                              _ptr(probes), _ptr(stats), _ptr(workspace), _stream()))
+    if want_probes:
+        return ids, dist, probes
+    return ids, dist
+
+
+def search_noalloc(index: Index, q, k_max: int, nprobe_max: int, eps0: float = 2.1,
+                   method: int = ADSAMPLING, K=None, nprobe=None, rerank: int = 0,
+                   want_probes: bool = False, stats=None, out=None):
+    """ads_search_noalloc: the search with the library's file-scope scratch
+    array as workspace (no device allocation by the library).  Output buffers
+    are allocated here unless ``out`` = (ids, dist) is given."""
+    torch = _torch()
+    q = _dev(q, torch.float32)
+    nq = q.shape[0]
+    Kt = _dev(K, torch.int32) if K is not None else None
+    Nt = _dev(nprobe, torch.int32) if nprobe is not None else None
+    if out is None:
+        ids = torch.empty((nq, k_max), dtype=torch.int64, device="cuda")
+        dist = torch.empty((nq, k_max), dtype=torch.float32, device="cuda")
+    else:
+        ids, dist = out
+    probes = torch.empty((nq, nprobe_max), dtype=torch.int32, device="cuda") if want_probes else None
+    e = math.inf if eps0 is None else float(eps0)
+    _check(load().ads_search_noalloc(index.handle, _ptr(q), nq, _ptr(Kt), _ptr(Nt), int(k_max),
+                                     int(nprobe_max), e, int(method), int(rerank), _ptr(ids),
+                                     _ptr(dist), _ptr(probes), _ptr(stats), _stream()))
     if want_probes:
         return ids, dist, probes
     return ids, dist

@@ -1,9 +1,11 @@
 // Host side of the C ABI declared in include/ads.h: argument validation,
 // index construction, workspace layout and the launch sequence of a search.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -46,7 +48,7 @@ struct ads_index {
     int64_t n = 0;
     int D = 0, nlist = 0, dd = 0, nb = 0, storage = 0, keep_fp32 = 0, max_list = 0, metric = 0;
     float *norms = nullptr;      // [n] raw norms by id (cosine indexes)
-    float *P = nullptr;          // [D][D]
+    float *P = nullptr;          // [D][D]; NULL for an index of unrotated vectors
     float *cent_rot = nullptr;   // [nlist][D]
     float *cent_norm = nullptr;  // [nlist]
     int64_t *list_off = nullptr; // [nlist + 1]
@@ -342,8 +344,8 @@ extern "C" ads_status ads_ivf_build(const float *base, int64_t n, int32_t D, con
                                     hipStream_t stream, ads_index **out) {
     if (!out) return fail(ADS_EINVAL, "out must not be NULL");
     *out = nullptr;
-    if (!base || !P || !centroids || !assign)
-        return fail(ADS_EINVAL, "base, P, centroids and assign must not be NULL");
+    if (!base || !centroids || !assign)
+        return fail(ADS_EINVAL, "base, centroids and assign must not be NULL");
     if (n < 1 || n >= ((int64_t)1 << 31)) return fail(ADS_EINVAL, "n must be in [1, 2^31) (got %lld)", (long long)n);
     if (D < 1 || D % 4 != 0) return fail(ADS_EINVAL, "D must be a positive multiple of 4 (got %d)", D);
     if (nlist < 1) return fail(ADS_EINVAL, "nlist must be >= 1 (got %d)", nlist);
@@ -416,7 +418,7 @@ extern "C" ads_status ads_ivf_build(const float *base, int64_t n, int32_t D, con
             return st;                 \
         }                              \
     } while (0)
-    BUILD_TRY(dmalloc(&ix->P, (size_t)D * D, &ix->bytes), "alloc P");
+    if (P) BUILD_TRY(dmalloc(&ix->P, (size_t)D * D, &ix->bytes), "alloc P");
     BUILD_TRY(dmalloc(&ix->cent_rot, (size_t)nlist * D, &ix->bytes), "alloc centroids");
     BUILD_TRY(dmalloc(&ix->cent_norm, (size_t)nlist, &ix->bytes), "alloc centroid norms");
     BUILD_TRY(dmalloc(&ix->list_off, (size_t)nlist + 1, &ix->bytes), "alloc offsets");
@@ -430,14 +432,14 @@ extern "C" ads_status ads_ivf_build(const float *base, int64_t n, int32_t D, con
         BUILD_TRY(e, "alloc blocked layout");
     }
     if (keep_fp32) BUILD_TRY(dmalloc(&ix->rows32, (size_t)n * D, &ix->bytes), "alloc float32 rows");
-    BUILD_TRY(hipMalloc(&rot, sizeof(float) * (size_t)n * D), "alloc rotation scratch");
+    if (P) BUILD_TRY(hipMalloc(&rot, sizeof(float) * (size_t)n * D), "alloc rotation scratch");
     if (metric == ADS_METRIC_COSINE) {
         BUILD_TRY(dmalloc(&ix->norms, (size_t)n, &ix->bytes), "alloc norms");
         const size_t rows = (size_t)(n > nlist ? n : nlist);
         BUILD_TRY(hipMalloc(&unit, sizeof(float) * rows * D), "alloc normalisation scratch");
     }
 
-    BUILD_TRY(hipMemcpyAsync(ix->P, P, sizeof(float) * D * D, hipMemcpyDeviceToDevice, stream), "copy P");
+    if (P) BUILD_TRY(hipMemcpyAsync(ix->P, P, sizeof(float) * D * D, hipMemcpyDeviceToDevice, stream), "copy P");
     BUILD_TRY(hipMemcpyAsync(ix->list_off, off.data(), sizeof(int64_t) * (nlist + 1), hipMemcpyHostToDevice, stream), "upload offsets");
     BUILD_TRY(hipMemcpyAsync(ix->ids, ids.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream), "upload ids");
     BUILD_TRY(hipMemcpyAsync(ix->pos_of, pos_of.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream), "upload positions");
@@ -448,8 +450,9 @@ extern "C" ads_status ads_ivf_build(const float *base, int64_t n, int32_t D, con
         BUILD_TRY(launch_normalize(base, n, D, unit, ix->norms, stream), "normalise base");
         src = unit;
     }
-    BUILD_TRY(gemm_nt_f32(src, D, ix->P, D, rot, D, n, D, D, stream), "rotate base");
-    BUILD_TRY(launch_pack(storage, rot, ix->ids, ix->list_of_pos, ix->list_off, n, D, delta_d, ix->data,
+    // without P the index stores the vectors as given (IVF* / IVF**, Section 6.1)
+    if (P) BUILD_TRY(gemm_nt_f32(src, D, ix->P, D, rot, D, n, D, D, stream), "rotate base");
+    BUILD_TRY(launch_pack(storage, P ? rot : src, ix->ids, ix->list_of_pos, ix->list_off, n, D, delta_d, ix->data,
                           ix->rows32, stream), "pack lists");
     const float *csrc = centroids;
     if (metric == ADS_METRIC_COSINE) {
@@ -457,7 +460,11 @@ extern "C" ads_status ads_ivf_build(const float *base, int64_t n, int32_t D, con
         BUILD_TRY(launch_normalize(centroids, nlist, D, unit, nullptr, stream), "normalise centroids");
         csrc = unit;
     }
-    BUILD_TRY(gemm_nt_f32(csrc, D, ix->P, D, ix->cent_rot, D, nlist, D, D, stream), "rotate centroids");
+    if (P)
+        BUILD_TRY(gemm_nt_f32(csrc, D, ix->P, D, ix->cent_rot, D, nlist, D, D, stream), "rotate centroids");
+    else
+        BUILD_TRY(hipMemcpyAsync(ix->cent_rot, csrc, sizeof(float) * (size_t)nlist * D, hipMemcpyDeviceToDevice,
+                                 stream), "copy centroids");
     BUILD_TRY(launch_row_norms(ix->cent_rot, nlist, D, ix->cent_norm, stream), "centroid norms");
     BUILD_TRY(hipStreamSynchronize(stream), "synchronize build");
     (void)hipFree(rot);
@@ -469,6 +476,172 @@ extern "C" ads_status ads_ivf_build(const float *base, int64_t n, int32_t D, con
     return ADS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// k-means clustering of the index phase (Section 2.2.2)
+// ---------------------------------------------------------------------------
+
+namespace {
+
+uint64_t splitmix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Rows that seed the lists: the nlist rows whose SplitMix64 draws (counter
+// seed + (i + 1) * golden gamma) are smallest, in ascending draw order.
+std::vector<int32_t> kmeans_init_rows(int64_t n, int nlist, uint64_t seed) {
+    std::vector<std::pair<uint64_t, int32_t>> k((size_t)n);
+    for (int64_t i = 0; i < n; ++i)
+        k[(size_t)i] = {splitmix64(seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull), (int32_t)i};
+    std::partial_sort(k.begin(), k.begin() + nlist, k.end());
+    std::vector<int32_t> rows((size_t)nlist);
+    for (int j = 0; j < nlist; ++j) rows[(size_t)j] = k[(size_t)j].second;
+    return rows;
+}
+
+}  // namespace
+
+extern "C" ads_status ads_kmeans(const float *x, int64_t n, int32_t D, int32_t nlist, int32_t iters, uint64_t seed,
+                                 float *centroids, int32_t *assign, hipStream_t stream) {
+    if (!x || !centroids || !assign) return fail(ADS_EINVAL, "x, centroids and assign must not be NULL");
+    if (n < 1 || n >= ((int64_t)1 << 31)) return fail(ADS_EINVAL, "n must be in [1, 2^31) (got %lld)", (long long)n);
+    if (D < 1 || D > 4096) return fail(ADS_EINVAL, "D must be in [1, 4096] (got %d)", D);
+    if (nlist < 1 || nlist > n) return fail(ADS_EINVAL, "nlist must be in [1, n] (got %d)", nlist);
+    if (iters < 0) return fail(ADS_EINVAL, "iters must be >= 0 (got %d)", iters);
+    HIP_TRY(hipGetLastError(), "pending HIP error");
+    std::vector<int32_t> init;
+    try {
+        init = kmeans_init_rows(n, nlist, seed);
+    } catch (...) {
+        return fail(ADS_ENOMEM, "host allocation failed");
+    }
+    // chunk of rows whose centre products fit in 256 MB
+    int64_t chunk = ((int64_t)64 << 20) / nlist;
+    if (chunk < 1) chunk = 1;
+    if (chunk > n) chunk = n;
+    int32_t *rows = nullptr, *counts = nullptr;
+    float *xn = nullptr, *cn = nullptr, *dots = nullptr, *d2 = nullptr;
+    unsigned long long *best = nullptr;
+    hipError_t e = hipSuccess;
+    auto release = [&]() {
+        void *ptrs[] = {rows, counts, xn, cn, dots, d2, best};
+        for (void *p : ptrs)
+            if (p) (void)hipFree(p);
+    };
+#define KM_TRY(expr, what)                              \
+    do {                                                \
+        e = (expr);                                     \
+        if (e != hipSuccess) {                          \
+            (void)hipStreamSynchronize(stream);         \
+            release();                                  \
+            return e == hipErrorOutOfMemory ? fail(ADS_ENOMEM, "%s: out of device memory", what) \
+                                            : hip_fail(e, what); \
+        }                                               \
+    } while (0)
+    KM_TRY(hipMalloc(&rows, sizeof(int32_t) * nlist), "alloc init rows");
+    KM_TRY(hipMalloc(&counts, sizeof(int32_t) * nlist), "alloc counts");
+    KM_TRY(hipMalloc(&xn, sizeof(float) * n), "alloc row norms");
+    KM_TRY(hipMalloc(&cn, sizeof(float) * nlist), "alloc centre norms");
+    KM_TRY(hipMalloc(&dots, sizeof(float) * (size_t)chunk * nlist), "alloc centre products");
+    KM_TRY(hipMalloc(&d2, sizeof(float) * n), "alloc distances");
+    KM_TRY(hipMalloc(&best, sizeof(unsigned long long)), "alloc farthest key");
+    KM_TRY(hipMemcpyAsync(rows, init.data(), sizeof(int32_t) * nlist, hipMemcpyHostToDevice, stream), "upload rows");
+    KM_TRY(launch_gather_rows(x, D, rows, nlist, centroids, stream), "initial centres");
+    KM_TRY(launch_row_norms(x, n, D, xn, stream), "row norms");
+    std::vector<int32_t> hc((size_t)nlist);
+    for (int it = 0; it <= iters; ++it) {
+        // assignment to the nearest centre (ties to the lower id)
+        KM_TRY(launch_row_norms(centroids, nlist, D, cn, stream), "centre norms");
+        for (int64_t r0 = 0; r0 < n; r0 += chunk) {
+            const int64_t m = n - r0 < chunk ? n - r0 : chunk;
+            KM_TRY(gemm_nt_f32(x + r0 * D, D, centroids, D, dots, nlist, m, nlist, D, stream), "centre products");
+            KM_TRY(launch_argmin(dots, xn + r0, cn, m, nlist, assign + r0, d2 + r0, stream), "nearest centre");
+        }
+        if (it == iters) break;     // the final assignment gives the lists
+        // empty lists, in ascending id order, take the farthest member of the
+        // largest list (lower id, then lower row on ties)
+        KM_TRY(launch_counts(assign, n, nlist, counts, stream), "list sizes");
+        KM_TRY(hipMemcpyAsync(hc.data(), counts, sizeof(int32_t) * nlist, hipMemcpyDeviceToHost, stream), "sizes");
+        KM_TRY(hipStreamSynchronize(stream), "synchronize");
+        for (int j = 0; j < nlist; ++j) {
+            if (hc[(size_t)j] > 0) continue;
+            int big = 0;
+            for (int l = 1; l < nlist; ++l)
+                if (hc[(size_t)l] > hc[(size_t)big]) big = l;
+            if (hc[(size_t)big] < 2) break;     // nothing to move
+            unsigned long long key = 0;
+            KM_TRY(launch_farthest(assign, d2, n, big, best, stream), "farthest member");
+            KM_TRY(hipMemcpyAsync(&key, best, sizeof key, hipMemcpyDeviceToHost, stream), "farthest key");
+            KM_TRY(hipStreamSynchronize(stream), "synchronize");
+            const int32_t row = (int32_t)(0xffffffffu - (uint32_t)(key & 0xffffffffu));
+            KM_TRY(hipMemcpy(assign + row, &j, sizeof(int32_t), hipMemcpyHostToDevice), "move row");
+            hc[(size_t)big] -= 1;
+            hc[(size_t)j] = 1;
+        }
+        // every centre moves to the mean of its members
+        KM_TRY(launch_update_centres(x, n, D, assign, nlist, centroids, stream), "centre update");
+    }
+    KM_TRY(hipStreamSynchronize(stream), "synchronize k-means");
+#undef KM_TRY
+    release();
+    return ADS_OK;
+}
+
+extern "C" ads_status ads_build_ivf(const float *base, int64_t n, int32_t D, const float *P, int32_t nlist,
+                                    int32_t iters, uint64_t seed, int32_t delta_d, int32_t storage,
+                                    int32_t keep_fp32, int32_t metric, float *centroids_out, int32_t *assign_out,
+                                    hipStream_t stream, ads_index **out) {
+    if (!out) return fail(ADS_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    if (!base) return fail(ADS_EINVAL, "base must not be NULL");
+    if (metric != ADS_METRIC_L2 && metric != ADS_METRIC_COSINE) return fail(ADS_EINVAL, "unknown metric %d", metric);
+    if (n < 1 || n >= ((int64_t)1 << 31)) return fail(ADS_EINVAL, "n must be in [1, 2^31) (got %lld)", (long long)n);
+    if (nlist < 1 || nlist > n) return fail(ADS_EINVAL, "nlist must be in [1, n] (got %d)", nlist);
+    if (D < 1 || D > 4096 || D % 4 != 0) return fail(ADS_EINVAL, "D must be a multiple of 4 in [4, 4096] (got %d)", D);
+    if (storage != ADS_F32 && storage != ADS_BF16 && storage != ADS_F16)
+        return fail(ADS_EINVAL, "unknown storage type %d", storage);
+    if (!valid_dd(delta_d)) return fail(ADS_EUNSUPPORTED, "delta_d must be one of 8, 16, 32, 64 (got %d)", delta_d);
+    if (D % delta_d != 0) return fail(ADS_EINVAL, "delta_d=%d must divide D=%d", delta_d, D);
+    if (iters < 0) return fail(ADS_EINVAL, "iters must be >= 0 (got %d)", iters);
+    float *cent = centroids_out, *unit = nullptr;
+    int32_t *asg = assign_out;
+    bool own_c = false, own_a = false;
+    auto release = [&]() {
+        if (own_c && cent) (void)hipFree(cent);
+        if (own_a && asg) (void)hipFree(asg);
+        if (unit) (void)hipFree(unit);
+    };
+    hipError_t e = hipSuccess;
+    if (!cent) {
+        e = hipMalloc(&cent, sizeof(float) * (size_t)nlist * D);
+        own_c = true;
+    }
+    if (e == hipSuccess && !asg) {
+        e = hipMalloc(&asg, sizeof(int32_t) * (size_t)n);
+        own_a = true;
+    }
+    // cosine: the lists are k-means clusters of the normalised vectors
+    const float *kx = base;
+    if (e == hipSuccess && metric == ADS_METRIC_COSINE) {
+        e = hipMalloc(&unit, sizeof(float) * (size_t)n * D);
+        if (e == hipSuccess) e = launch_normalize(base, n, D, unit, nullptr, stream);
+        kx = unit;
+    }
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(stream);
+        release();
+        return e == hipErrorOutOfMemory ? fail(ADS_ENOMEM, "k-means buffers: out of device memory")
+                                        : hip_fail(e, "k-means buffers");
+    }
+    ads_status st = ads_kmeans(kx, n, D, nlist, iters, seed, cent, asg, stream);
+    if (st == ADS_OK)
+        st = ads_ivf_build(base, n, D, P, cent, nlist, asg, delta_d, storage, keep_fp32, metric, stream, out);
+    (void)hipStreamSynchronize(stream);
+    release();
+    return st;
+}
+
 extern "C" ads_status ads_index_info(const ads_index *ix, ads_index_desc *info) {
     if (!ix || !info) return fail(ADS_EINVAL, "index and info must not be NULL");
     info->n = ix->n;
@@ -477,6 +650,7 @@ extern "C" ads_status ads_index_info(const ads_index *ix, ads_index_desc *info) 
     info->delta_d = ix->dd;
     info->storage = ix->storage;
     info->has_fp32_copy = ix->rows32 != nullptr;
+    info->rotated = ix->P != nullptr;
     info->max_list = ix->max_list;
     info->metric = ix->metric;
     info->device_bytes = ix->bytes;
@@ -533,6 +707,8 @@ extern "C" ads_status ads_dco_batch(const ads_index *ix, const float *q_rot, con
     if (method < 0 || method > 2) return fail(ADS_EINVAL, "unknown method %d", method);
     if (source != 0 && source != 1) return fail(ADS_EINVAL, "source must be 0 or 1");
     if (source == 1 && !ix->rows32) return fail(ADS_EINVAL, "source 1 needs an index built with keep_fp32 = 1");
+    if (!ix->P && method == ADS_METHOD_ADSAMPLING && !std::isinf(eps0))
+        return fail(ADS_EINVAL, "ADSampling needs a rotated index (built with P); this one stores unrotated vectors");
     HIP_TRY(hipGetLastError(), "pending HIP error");
     const float r2 = r * r;
     HIP_TRY(launch_dco(ix->storage, ix->data, ix->rows32, source, ix->list_off, ix->list_of_pos, ix->pos_of,
@@ -554,13 +730,18 @@ extern "C" ads_status ads_dco_batch_ip(const ads_index *ix, const float *q, cons
     if (!(eps0 >= 0.f)) return fail(ADS_EINVAL, "eps0 must be >= 0 (got %g)", (double)eps0);
     if (delta_d < 1 || delta_d > ix->D) return fail(ADS_EINVAL, "delta_d must be in [1, D=%d] (got %d)", ix->D, delta_d);
     if (method < 0 || method > 2) return fail(ADS_EINVAL, "unknown method %d", method);
+    if (!ix->P && method == ADS_METHOD_ADSAMPLING && !std::isinf(eps0))
+        return fail(ADS_EINVAL, "ADSampling needs a rotated index (built with P); this one stores unrotated vectors");
     HIP_TRY(hipGetLastError(), "pending HIP error");
     const int D = ix->D;
     float *scr = nullptr;
     HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&scr), sizeof(float) * (2 * (size_t)D + 64), stream), "scratch");
     float *qn = scr, *qr = scr + D, *qnorm = scr + 2 * D;
     hipError_t e = launch_normalize(q, 1, D, qn, qnorm, stream);
-    if (e == hipSuccess) e = gemm_nt_f32(qn, D, ix->P, D, qr, D, 1, D, D, stream);
+    if (e == hipSuccess) {
+        if (ix->P) e = gemm_nt_f32(qn, D, ix->P, D, qr, D, 1, D, D, stream);
+        else e = hipMemcpyAsync(qr, qn, sizeof(float) * D, hipMemcpyDeviceToDevice, stream);
+    }
     IpArgs ipa{ix->norms, qnorm, r};
     if (e == hipSuccess)
         e = launch_dco(ix->storage, ix->data, ix->rows32, 0, ix->list_off, ix->list_of_pos, ix->pos_of, ix->n, D,
@@ -587,6 +768,8 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
     if (!q || !ids || !dist) return fail(ADS_EINVAL, "q, ids and dist must not be NULL");
     if (!(eps0 >= 0.f)) return fail(ADS_EINVAL, "eps0 must be >= 0 (got %g)", (double)eps0);
     if (method < 0 || method > 2) return fail(ADS_EINVAL, "unknown method %d", method);
+    if (!ix->P && method == ADS_METHOD_ADSAMPLING && !std::isinf(eps0))
+        return fail(ADS_EINVAL, "ADSampling needs a rotated index (built with P); this one stores unrotated vectors");
     if (workspace && (reinterpret_cast<uintptr_t>(workspace) & 255u))
         return fail(ADS_EINVAL, "workspace must be 256-byte aligned");
     HIP_TRY(hipGetLastError(), "pending HIP error");
@@ -651,7 +834,9 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
             SEARCH_TRY(launch_normalize(q, nq, D, qunit, nullptr, stream), "normalise queries");
             qsrc = qunit;
         }
-        SEARCH_TRY(gemm_nt_f32(qsrc, D, ix->P, D, qrot, D, nq, D, D, stream), "rotate queries");
+        if (ix->P) SEARCH_TRY(gemm_nt_f32(qsrc, D, ix->P, D, qrot, D, nq, D, D, stream), "rotate queries");
+        else SEARCH_TRY(hipMemcpyAsync(qrot, qsrc, sizeof(float) * (size_t)nq * D, hipMemcpyDeviceToDevice,
+                                       stream), "copy queries");
     }
     // 2. probe selection
     {
@@ -746,6 +931,59 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
     }
 #undef SEARCH_TRY
     return done(hipSuccess, "");
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free searches: the workspace is a file-scope device array.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// On the host this name is only a stand-in: kernels get the device address
+// taken with hipGetSymbolAddress, once per device, with that device current.
+// Every GPU the library runs on holds its own copy until the process ends.
+__device__ __align__(256) unsigned char scratch[ADS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[SCRATCH_DEVICES] = {};
+
+ads_status scratch_address(void **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "current device");
+    if (dev < 0 || dev >= SCRATCH_DEVICES)
+        return fail(ADS_EUNSUPPORTED, "device %d: allocation-free searches support devices 0..%d", dev,
+                    SCRATCH_DEVICES - 1);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "scratch symbol address");
+        if (!p) return fail(ADS_EHIP, "scratch symbol address: null pointer");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return ADS_OK;
+}
+
+}  // namespace
+
+extern "C" ads_status ads_search_noalloc(const ads_index *ix, const float *q, int32_t nq, const int32_t *K,
+                                         const int32_t *nprobe, int32_t k_max, int32_t nprobe_max, float eps0,
+                                         int32_t method, int32_t rerank, int64_t *ids, float *dist,
+                                         int32_t *probes_out, int64_t *stats, hipStream_t stream) {
+    ads_status st = check_search_args(ix, nq, k_max, nprobe_max, rerank);
+    if (st != ADS_OK) return st;
+    const size_t need = layout_for(ix, nq, k_max, nprobe_max, rerank).total;
+    if (need > (size_t)ADS_NOALLOC_SCRATCH_BYTES)
+        return fail(ADS_EINVAL,
+                    "allocation-free search needs %zu bytes of workspace for these sizes; the scratch array "
+                    "holds %llu (use ads_search with a workspace)",
+                    need, (unsigned long long)ADS_NOALLOC_SCRATCH_BYTES);
+    void *ws = nullptr;
+    st = scratch_address(&ws);
+    if (st != ADS_OK) return st;
+    return ads_search(ix, q, nq, K, nprobe, k_max, nprobe_max, eps0, method, rerank, ids, dist, probes_out,
+                      stats, ws, stream);
 }
 
 struct ads_plan {

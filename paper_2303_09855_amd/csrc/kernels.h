@@ -59,4 +59,14 @@ hipError_t launch_pack(int dtype, const float *rot, const int32_t *ids, const in
 
 hipError_t launch_row_norms(const float *x, int64_t n, int D, float *out, hipStream_t s);
 
+// k-means (kmeans.hip)
+hipError_t launch_gather_rows(const float *x, int D, const int32_t *rows, int m, float *out, hipStream_t s);
+hipError_t launch_argmin(const float *dots, const float *xn, const float *cn, int64_t m, int nlist,
+                         int32_t *assign, float *d2, hipStream_t s);
+hipError_t launch_counts(const int32_t *assign, int64_t n, int nlist, int32_t *counts, hipStream_t s);
+hipError_t launch_farthest(const int32_t *assign, const float *d2, int64_t n, int l, unsigned long long *best,
+                           hipStream_t s);
+hipError_t launch_update_centres(const float *x, int64_t n, int D, const int32_t *assign, int nlist, float *cent,
+                                 hipStream_t s);
+
 }  // namespace ads

@@ -210,6 +210,40 @@ def test_search_pdscanning_ids_equal_oracle(ads, request, fixture, nprobe, K, dd
         ix.free()
 
 
+@pytest.mark.parametrize("fixture,nprobe,K,dd", [("ivf960", 8, 10, 16), ("ivf128", 12, 100, 32)])
+def test_unrotated_pdscanning_index_equals_oracle(ads, request, fixture, nprobe, K, dd):
+    """IVF* / IVF** (Section 6.1): PDScanning on the original coordinates of an
+    index built without a rotation.  Exact, so the ids equal the oracle's
+    PDScanning search on the raw FP64 vectors outside the tie band; ADSampling
+    is refused on such an index."""
+    w, _ = request.getfixturevalue(fixture)
+    ix = ads.ivf_build(w.x, None, w.cent, w.assign, delta_d=dd, storage=ads.F32, keep_fp32=False)
+    try:
+        assert ix.info()["rotated"] == 0
+        stats = torch.zeros(ads.NSTATS, dtype=torch.int64, device="cuda")
+        ids, dist, probes = ads.search(ix, w.q, K, nprobe, eps0=math.inf, method=ads.PDSCANNING,
+                                       want_probes=True, stats=stats)
+        ids, dist, probes, st = _np(ids), _np(dist), _np(probes), _np(stats)
+        xd, qd, cd = (w.x.astype(np.float64), w.q.astype(np.float64), w.cent.astype(np.float64))
+        pr, d2 = oracle.probes(qd, cd, nprobe)
+        nbad = sum(not probes_agree(probes[i], pr[i], qd[i], cd, d2[i]) for i in range(w.nq))
+        assert nbad <= max(1, w.nq // 10)
+        o_ids, o_d, o_st = oracle.ivf_search(xd, qd, w.off, w.members, pr, K, math.inf, dd,
+                                             method=oracle.METHOD_PDS)
+        for i in range(w.nq):
+            if set(probes[i].tolist()) == set(pr[i].tolist()):
+                assert tie_band_equal(ids[i], dist[i], o_ids[i], o_d[i]), i
+        ex = w.exact(ids)
+        v = ids >= 0
+        assert np.all(np.abs(dist[v] - ex[v]) <= 1e-5 * ex[v])
+        assert st[ads.STAT_DCOS] == o_st[:, 0].sum()
+        assert st[ads.STAT_DIMS] < st[ads.STAT_DCOS] * w.D
+        with pytest.raises(ads.AdsError):
+            ads.search(ix, w.q, K, nprobe, eps0=2.1)
+    finally:
+        ix.free()
+
+
 def test_flat_search_matches_oracle(ads):
     """The flat ADSampling scan (one list, fixed order; N = 10,000, D = 128
     integer mixture, K = 10, delta_d = 32, eps0 = 2.1): ids equal the oracle's

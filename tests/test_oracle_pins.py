@@ -415,6 +415,62 @@ def test_recall_and_ratio_metrics_hand_cases():
 
 
 # --------------------------------------------------------------------------
+# Section 2.2.2 index phase: k-means
+# --------------------------------------------------------------------------
+
+def _kmeans_golden():
+    with open(os.path.join(GOLDEN, "kmeans_tiny.json")) as fh:
+        return json.load(fh)
+
+
+def test_splitmix64_published_outputs():
+    g = _kmeans_golden()["splitmix64"]
+    st = g["state"]
+    out = []
+    for _ in range(3):
+        st = (st + 0x9E3779B97F4A7C15) % (1 << 64)
+        out.append(oracle.splitmix64(st))
+    assert out == g["outputs"]
+
+
+@pytest.mark.parametrize("case", _kmeans_golden()["cases"], ids=lambda c: c["why"][:30])
+def test_kmeans_golden_cases(case):
+    c, lab = oracle.kmeans(np.array(case["x"], float), case["nlist"], case["iters"], init=case["init"])
+    assert lab.tolist() == case["assign"]
+    assert np.allclose(c, np.array(case["centres"], float), rtol=0, atol=1e-12)
+
+
+def test_kmeans_init_rows_distinct_and_seeded():
+    a = oracle.kmeans_init_rows(500, 40, 7)
+    assert len(set(a.tolist())) == 40 and a.min() >= 0 and a.max() < 500
+    assert np.array_equal(a, oracle.kmeans_init_rows(500, 40, 7))
+    assert not np.array_equal(a, oracle.kmeans_init_rows(500, 40, 8))
+    # the prefix property: the first rows of a smaller draw are the same rows
+    assert np.array_equal(oracle.kmeans_init_rows(500, 10, 7), a[:10])
+
+
+def test_kmeans_objective_never_increases():
+    """Lloyd's iterations never increase the sum of squared distances to the
+    assigned centres (assignment and mean steps each minimise it)."""
+    x = sd.lowrank(3000, 16, 71, 72, latent=4, noise=0.2)
+    prev = np.inf
+    for it in range(0, 6):
+        c, lab = oracle.kmeans(x, 12, it, seed=5)
+        obj = float(np.sum((x.astype(np.float64) - c[lab]) ** 2))
+        assert obj <= prev * (1 + 1e-12)
+        prev = obj
+
+
+def test_kmeans_one_list_per_row_is_the_identity():
+    x = np.random.default_rng(3).standard_normal((30, 5))
+    c, lab = oracle.kmeans(x, 30, 2, seed=11)
+    init = oracle.kmeans_init_rows(30, 30, 11)
+    assert np.array_equal(np.sort(lab), np.arange(30))
+    assert np.array_equal(c[lab], x)
+    assert np.array_equal(lab[init], np.arange(30))
+
+
+# --------------------------------------------------------------------------
 # Section 8, extension (1): cosine similarity and inner product
 # --------------------------------------------------------------------------
 
