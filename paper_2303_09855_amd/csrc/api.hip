@@ -37,7 +37,7 @@ __global__ void output_kernel(const uint64_t *tk, const int32_t *kq, int nq, int
                               int64_t *ids, float *dist);
 __global__ void rerank_kernel(const uint64_t *tk, const int32_t *kq, const int32_t *keff,
                               const float *rows32, const int32_t *pos_of, const float *qrot, int D,
-                              int kcap, int k_max, int64_t *ids, float *dist);
+                              int dd, int kcap, int k_max, int64_t *ids, float *dist);
 __global__ void probes_out_kernel(const int32_t *probes, const int32_t *npq, int nq, int nprobe_max,
                                   int32_t *out);
 }  // namespace ads
@@ -165,7 +165,7 @@ int qw_for(int kcap) {
     return auto_qw;
 }
 
-constexpr int KCAP_MAX = 512;
+constexpr int KCAP_MAX = KCAP_LIMIT;
 // Default of the prefetch_units knob: sweeps with fewer work units than this
 // run the prefetching scan instantiation.
 constexpr int64_t PREFETCH_UNITS = 8192;
@@ -917,7 +917,7 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
         if (rerank) {
             const size_t sh = sizeof(uint64_t) * (size_t)next_pow2(L.kcap);
             hipLaunchKernelGGL(rerank_kernel, dim3(nq), dim3(ADS_WG), sh, stream, tk, kq, keff, ix->rows32,
-                               ix->pos_of, qrot, D, L.kcap, k_max, ids, dist);
+                               ix->pos_of, qrot, D, ix->dd, L.kcap, k_max, ids, dist);
         } else {
             hipLaunchKernelGGL(output_kernel, dim3(grid_for((int64_t)nq * k_max)), dim3(ADS_WG), 0, stream, tk, kq,
                                nq, k_max, L.kcap, ids, dist);

@@ -23,6 +23,8 @@ __device__ __forceinline__ uint64_t make_key(float s, uint32_t id) {
 __device__ __forceinline__ float key_dist2(uint64_t k) { return __uint_as_float((uint32_t)(k >> 32)); }
 __device__ __forceinline__ uint32_t key_id(uint64_t k) { return (uint32_t)k; }
 constexpr uint64_t KEY_NONE = ~0ull;
+// largest KNN-set capacity of a search (k_max, times 4 with the rerank)
+constexpr int KCAP_LIMIT = 512;
 
 // ---------------------------------------------------------------------------
 // Test coefficients.  For a DCO that has sampled d of D coordinates with
@@ -178,6 +180,89 @@ __device__ uint64_t radix_kth(Get get, int n, int k, uint32_t *hist, uint32_t *m
         }
     }
     return prefix;
+}
+
+// ---------------------------------------------------------------------------
+// k-th smallest (1-based) of n uint64 keys get(i), 1 <= k <= n, for a
+// workgroup of NT threads (a multiple of 64, every thread calls it): radix
+// select over bytes from the most significant one, stopping as soon as one key
+// carries the selected prefix.  hist: LDS [256] uint32; misc: LDS [4] uint32;
+// found: LDS uint64.  All threads return the key.
+// ---------------------------------------------------------------------------
+template <int NT, class Get>
+__device__ uint64_t group_kth(Get get, int n, int k, uint32_t *hist, uint32_t *misc, uint64_t *found) {
+    uint64_t prefix = 0, pmask = 0;
+    uint32_t kk = (uint32_t)k;
+    const int t = threadIdx.x;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        for (int b = t; b < 256; b += NT) hist[b] = 0;
+        __syncthreads();
+        for (int i = t; i < n; i += NT) {
+            const uint64_t key = get(i);
+            if ((key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (t < 64) {
+            // lane t owns bins 4t .. 4t+3; the bin whose cumulative range covers kk wins
+            const uint32_t h0 = hist[4 * t], h1 = hist[4 * t + 1], h2 = hist[4 * t + 2], h3 = hist[4 * t + 3];
+            const uint32_t sum = h0 + h1 + h2 + h3;
+            uint32_t x = sum;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(x, o);
+                if (t >= o) x += y;
+            }
+            const uint32_t c0 = x - sum, c1 = c0 + h0, c2 = c1 + h1, c3 = c2 + h2, c4 = c3 + h3;
+            if (c0 < kk && kk <= c1) { misc[0] = 4 * t; misc[1] = kk - c0; misc[2] = h0; }
+            if (c1 < kk && kk <= c2) { misc[0] = 4 * t + 1; misc[1] = kk - c1; misc[2] = h1; }
+            if (c2 < kk && kk <= c3) { misc[0] = 4 * t + 2; misc[1] = kk - c2; misc[2] = h2; }
+            if (c3 < kk && kk <= c4) { misc[0] = 4 * t + 3; misc[1] = kk - c3; misc[2] = h3; }
+        }
+        __syncthreads();
+        const uint32_t sel = misc[0], cnt = misc[2];
+        kk = misc[1];
+        prefix |= (uint64_t)sel << shift;
+        pmask |= (uint64_t)0xff << shift;
+        __syncthreads();
+        if (cnt == 1) {
+            for (int i = t; i < n; i += NT) {
+                const uint64_t key = get(i);
+                if ((key & pmask) == prefix) *found = key;
+            }
+            __syncthreads();
+            const uint64_t r = *found;
+            __syncthreads();
+            return r;
+        }
+    }
+    return prefix;
+}
+
+// Exclusive prefix sum of one int per thread over a workgroup of W waves (every
+// thread calls it); *total receives the sum.  wtot: LDS [W] ints.  Starts and
+// ends with a workgroup barrier, so consecutive calls may share wtot.
+template <int W>
+__device__ int group_excl_scan(int v, int *wtot, int &total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    __syncthreads();
+    if (lane == 63) wtot[w] = x;
+    __syncthreads();
+    int base = 0, tot = 0;
+#pragma unroll
+    for (int ww = 0; ww < W; ++ww) {
+        const int t = wtot[ww];
+        base += ww < w ? t : 0;
+        tot += t;
+    }
+    total = tot;
+    __syncthreads();
+    return base + x - v;
 }
 
 __host__ __device__ inline int next_pow2(int v) {

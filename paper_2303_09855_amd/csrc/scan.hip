@@ -443,11 +443,14 @@ __global__ void output_kernel(const uint64_t *tk, const int32_t *kq, int nq, int
 }
 
 // Low-precision mode: recompute the keff candidates' distances from the
-// float32 rows (same summation order as the float32 scan) and keep the best K.
+// float32 rows and keep the best K.  The sum is the scan's canonical one
+// (per-block partials of dd coordinates, each from zero with fused
+// multiply-adds in coordinate order, added in block order), so a reranked
+// distance equals the float32 scan's distance of the same pair bit for bit.
 __global__ __launch_bounds__(ADS_WG) void rerank_kernel(const uint64_t *tk, const int32_t *kq,
                                                        const int32_t *keff, const float *rows32,
                                                        const int32_t *pos_of, const float *qrot,
-                                                       int D, int kcap, int k_max, int64_t *ids,
+                                                       int D, int dd, int kcap, int k_max, int64_t *ids,
                                                        float *dist) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     uint64_t *buf = reinterpret_cast<uint64_t *>(smem_raw);
@@ -463,9 +466,13 @@ __global__ __launch_bounds__(ADS_WG) void rerank_kernel(const uint64_t *tk, cons
                 uint32_t id = key_id(c);
                 const float *row = rows32 + (int64_t)pos_of[id] * D;
                 float s = 0.f;
-                for (int t = 0; t < D; ++t) {
-                    float df = row[t] - qr[t];
-                    s = __fmaf_rn(df, df, s);
+                for (int b0 = 0; b0 < D; b0 += dd) {
+                    float pb = 0.f;
+                    for (int t = b0; t < b0 + dd; ++t) {
+                        float df = row[t] - qr[t];
+                        pb = __fmaf_rn(df, df, pb);
+                    }
+                    s += pb;
                 }
                 key = make_key(s, id);
             }

@@ -49,9 +49,71 @@ struct ScanSmem {
     float thr[W][QW];               // rejection thresholds of the current block
     // shared by the unit
     float r2s[QW];
-    int qidx[QW], qrank[QW], qk[QW], tkcnt[QW], tkmax[QW];
+    int qidx[QW], qrank[QW], qk[QW], tkcnt[QW];
+    uint64_t tkkth[QW];             // the K-th key of a full local KNN set
+    uint64_t found;
+    uint32_t misc[4];
+    uint32_t hist[256];             // radix-select histogram of the fold
     // followed by float coef[nb] and uint64 tk[QW][kcap]
 };
+
+// Folds a round's positives into each query's local KNN set: the set becomes
+// the K smallest keys of the set and the new positives, selected by the whole
+// workgroup (radix select of the K-th key over the union, then the kept new
+// keys fill the holes).  At the end of a round of tiles a full set lowers its
+// query's threshold to the K-th distance.  Kept out of line: it runs once per
+// round, and inlined it would add register pressure to the scan loop.
+template <int W, class Smem>
+__device__ __attribute__((noinline)) void fold_round(Smem &sm, uint64_t *tk, int kcap, int qc, bool round_end) {
+    const int tid = threadIdx.x;
+    for (int j = 0; j < qc; ++j) {
+        const int K = sm.qk[j];
+        if (K <= 0) continue;
+        int m = 0;
+        for (int ww = 0; ww < W; ++ww) m += sm.pcnt[ww][j];
+        uint64_t *mytk = tk + (int64_t)j * kcap;
+        const int c = sm.tkcnt[j];
+        if (m > 0) {
+            auto newkey = [&](int i) -> uint64_t {
+                int ww = 0;
+                while (i >= sm.pcnt[ww][j]) i -= sm.pcnt[ww][j], ++ww;
+                return sm.pos[ww][j][i];
+            };
+            auto get = [&](int i) -> uint64_t { return i < c ? mytk[i] : newkey(i - c); };
+            const int n = c + m;
+            // the K-th key of the union, once the set will be full
+            const uint64_t kth = n >= K ? group_kth<64 * W>(get, n, K, sm.hist, sm.misc, &sm.found) : KEY_NONE;
+            // keys are distinct (distinct ids), so exactly min(n, K) keys are
+            // <= kth.  The kept new keys (at most one per thread: m <= 64 W)
+            // fill the holes of the set: slots >= c, and old keys > kth.
+            const uint64_t nk = tid < m ? newkey(tid) : KEY_NONE;
+            const bool keepnew = tid < m && nk <= kth;
+            const int kn = n < K ? n : K;
+            int nh = 0;
+            for (int sl = tid; sl < kn; sl += 64 * W) nh += (sl >= c || mytk[sl] > kth);
+            int htot, ntot;
+            const int hbase = group_excl_scan<W>(nh, reinterpret_cast<int *>(sm.misc), htot);
+            const int nrank = group_excl_scan<W>(keepnew ? 1 : 0, reinterpret_cast<int *>(sm.misc), ntot);
+            // hole positions by rank, in the (consumed) positive buffers
+            int *holes = reinterpret_cast<int *>(&sm.pos[0][0][0]);
+            int hr = hbase;
+            for (int sl = tid; sl < kn; sl += 64 * W)
+                if (sl >= c || mytk[sl] > kth) holes[hr++] = sl;
+            __syncthreads();
+            if (keepnew) mytk[holes[nrank]] = nk;
+            if (tid == 0) {
+                sm.tkcnt[j] = kn;
+                sm.tkkth[j] = kth;
+            }
+            __syncthreads();
+        }
+        if (tid == 0 && round_end && sm.tkcnt[j] == K) {
+            const float kth = key_dist2(sm.tkkth[j]);
+            if (kth < sm.r2s[j]) sm.r2s[j] = kth;
+        }
+    }
+    __syncthreads();
+}
 
 // PF: fetch the next block of the dense phase while the current one is
 // evaluated (more registers; for sweeps with fewer units than wave slots).
@@ -99,7 +161,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(PF ? 2 :
             }
             sm.qk[tid] = kq;
             sm.tkcnt[tid] = 0;
-            sm.tkmax[tid] = 0;
+            sm.tkkth[tid] = KEY_NONE;
         }
         __syncthreads();
         if (tid == 0) {
@@ -308,36 +370,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(PF ? 2 :
                 my_pos += so.pos;
             }
             __syncthreads();
-            // fold the round's positives into each query's local KNN set
-            if (tid < qc && sm.qk[tid] > 0) {
-                const int j = tid, K = sm.qk[j];
-                uint64_t *mytk = tk + (int64_t)j * kcap;
-                int c = sm.tkcnt[j], mx = sm.tkmax[j];
-                for (int ww = 0; ww < W; ++ww) {
-                    const int np = sm.pcnt[ww][j];
-                    for (int p = 0; p < np; ++p) {
-                        const uint64_t key = sm.pos[ww][j][p];
-                        if (c < K) {
-                            mytk[c++] = key;
-                            if (c == K) {
-                                mx = 0;
-                                for (int t = 1; t < K; ++t) if (mytk[t] > mytk[mx]) mx = t;
-                            }
-                        } else if (key < mytk[mx]) {
-                            mytk[mx] = key;
-                            mx = 0;
-                            for (int t = 1; t < K; ++t) if (mytk[t] > mytk[mx]) mx = t;
-                        }
-                    }
-                }
-                sm.tkcnt[j] = c;
-                sm.tkmax[j] = mx;
-                if (round_end && c == K) {
-                    const float kth = key_dist2(mytk[mx]);
-                    if (kth < sm.r2s[j]) sm.r2s[j] = kth;
-                }
-            }
-            __syncthreads();
+            fold_round<W>(sm, tk, kcap, qc, round_end);
         }
         // publish the unit's per-query KNN sets for the merge
         for (int i = tid; i < qc * kcap; i += 64 * W) {

@@ -363,6 +363,20 @@ def test_low_precision_storage_with_rerank(ads, ivf960, storage):
         errs.extend((np.abs(dist[i][v] - ex) / ex).tolist())
     assert max(errs) <= 1e-5
     assert oracle.recall(ids, ex_all, gt, K) >= oracle.recall(o_ids, w.exact(o_ids), gt, K) - 0.01
+    # the rerank sums in the scan's canonical order: a reranked distance equals
+    # the float32 search's distance of the same pair bit for bit
+    _, ix32 = ivf960
+    f_ids, f_dist = ads.search(ix32, w.q, K, nprobe, eps0=math.inf)
+    f_ids, f_dist = _np(f_ids), _np(f_dist)
+    shared = 0
+    for i in range(w.nq):
+        common = {int(j): float(d) for j, d in zip(f_ids[i], f_dist[i]) if j >= 0}
+        for j, d in zip(ids[i], dist[i]):
+            if int(j) in common:
+                assert np.float32(d) == np.float32(common[int(j)]), (i, j)
+                shared += 1
+    assert shared > w.nq * K // 2
+    ix.free()
 
 
 def test_search_distances_equal_dco_batch(ads, ivf960):
