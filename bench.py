@@ -74,6 +74,7 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=20000, help="serve mode: requests per rate")
     ap.add_argument("--serve-nprobe", default="32,64",
                     help="serve mode: per-request nprobe drawn uniformly from this list")
+    ap.add_argument("--max-batch", type=int, default=512, help="serve mode: largest batch")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device-to-device copy first (reference kernel "
                          "of known size for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -323,7 +324,7 @@ def serve(args, w, ix, q, gt, x):
         Ks = rng.choice([10, 100], size=n)
         Ps = rng.choice(nps, size=n)
         reqs = [Request(i, q[qi[i]], int(Ks[i]), int(Ps[i]), float(t[i])) for i in range(n)]
-        srv = Server(ix, k_max=100, nprobe_max=max(nps), eps0=args.eps0, max_batch=1024, n_streams=3)
+        srv = Server(ix, k_max=100, nprobe_max=max(nps), eps0=args.eps0, max_batch=args.max_batch, n_streams=3)
         res, lat, st = srv.run(reqs)
         # recall@10 of the first 10 results of every request against the exact top-10
         ids = np.stack([np.pad(res[i][0][:10], (0, max(0, 10 - len(res[i][0][:10]))),
@@ -339,7 +340,8 @@ def serve(args, w, ix, q, gt, x):
             "value": out[-1]["qps"], "unit": "queries/s", "n_gpus": 1, "higher_is_better": True,
             "dtype": "f32", "data": "synthetic",
             "config": {"workload": f"{w.name} index, requests cycle its {w.nq} queries, "
-                                   f"K in {{10,100}} (one queue per K class), nprobe in {nps}, batches <= 1024, 3 streams"},
+                                   f"K in {{10,100}} (one queue per K class), nprobe in {nps}, "
+                                   f"batches <= {args.max_batch}, 3 streams"},
             "rates": out}
     print(json.dumps(line), flush=True)
     ix.free()

@@ -77,6 +77,7 @@ typedef struct {
     int32_t metric;         /* ads_metric */
     int64_t device_bytes;   /* device memory held by the index */
     int32_t rotated;        /* 1 if built with a rotation P, 0 for unrotated vectors */
+    int32_t a1_dims;        /* leading coordinates stored block-major (IVF++ array A1) */
 } ads_index_desc;
 
 /* Counters accumulated by ads_search / ads_dco_batch into a caller buffer of
@@ -145,10 +146,13 @@ ads_status ads_rotate(const float *P, int32_t D, const float *X, int64_t n, floa
  *              queries and report distances between unit vectors
  *              (cosine similarity = 1 - dist^2 / 2).
  *   out        host pointer receiving the new index.
- * Layout: the rotated vectors of list l are stored as [block][vector][delta_d]
- * (all vectors' first block contiguous, then the second block, ...): the
- * cache-friendly arrangement of Section 5.2 generalised from two arrays to
- * one array per block.  Within a list, vectors keep ascending id order.
+ * Layout (IVF++, Section 5.2): for list l, the first a1_dims = min(D, max(
+ * delta_d, 128 rounded down to delta_d)) coordinates of all its vectors are
+ * stored block by block, [block][vector][delta_d] (the paper's array A1, its
+ * first d1 coordinates of all candidates; the scan reads them a 64-vector
+ * tile at a time), and the remaining D - a1_dims coordinates vector by
+ * vector (array A2, so the later blocks of one candidate are contiguous).
+ * Within a list, vectors keep ascending id order.
  * Synchronises the stream once (the list sizes are needed on the host).
  * Errors: ADS_EINVAL (sizes, ids out of range), ADS_ENOMEM, ADS_EHIP.
  */

@@ -50,7 +50,7 @@ class IndexDesc(ctypes.Structure):
                 ("delta_d", ctypes.c_int32), ("storage", ctypes.c_int32),
                 ("has_fp32_copy", ctypes.c_int32), ("max_list", ctypes.c_int32),
                 ("metric", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
-                ("rotated", ctypes.c_int32)]
+                ("rotated", ctypes.c_int32), ("a1_dims", ctypes.c_int32)]
 
 
 _lib = None

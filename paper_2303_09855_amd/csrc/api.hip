@@ -47,6 +47,7 @@ using namespace ads;
 struct ads_index {
     int64_t n = 0;
     int D = 0, nlist = 0, dd = 0, nb = 0, storage = 0, keep_fp32 = 0, max_list = 0, metric = 0;
+    int b1 = 0;                  // blocks of the list-major region of the layout (layout_offset)
     float *norms = nullptr;      // [n] raw norms by id (cosine indexes)
     float *P = nullptr;          // [D][D]; NULL for an index of unrotated vectors
     float *cent_rot = nullptr;   // [nlist][D]
@@ -166,6 +167,13 @@ int qw_for(int kcap) {
 }
 
 constexpr int KCAP_MAX = KCAP_LIMIT;
+// Coordinates of every vector stored in the list-major region of the layout
+// (IVF++'s array A1): the dense phase of the scan reads these a tile at a
+// time; the rest is stored vector by vector for the pair-list phase.
+#ifndef ADS_A1_DIMS
+#define ADS_A1_DIMS 128
+#endif
+constexpr int A1_DIMS = ADS_A1_DIMS;
 // Default of the prefetch_units knob: sweeps with fewer work units than this
 // run the prefetching scan instantiation.
 constexpr int64_t PREFETCH_UNITS = 8192;
@@ -399,6 +407,9 @@ extern "C" ads_status ads_ivf_build(const float *base, int64_t n, int32_t D, con
     ix->nlist = nlist;
     ix->dd = delta_d;
     ix->nb = D / delta_d;
+    // the list-major region (A1) holds the first A1_DIMS coordinates
+    ix->b1 = A1_DIMS / delta_d < 1 ? 1 : A1_DIMS / delta_d;
+    if (ix->b1 > ix->nb) ix->b1 = ix->nb;
     ix->storage = storage;
     ix->keep_fp32 = keep_fp32;
     ix->max_list = max_list;
@@ -452,7 +463,7 @@ extern "C" ads_status ads_ivf_build(const float *base, int64_t n, int32_t D, con
     }
     // without P the index stores the vectors as given (IVF* / IVF**, Section 6.1)
     if (P) BUILD_TRY(gemm_nt_f32(src, D, ix->P, D, rot, D, n, D, D, stream), "rotate base");
-    BUILD_TRY(launch_pack(storage, P ? rot : src, ix->ids, ix->list_of_pos, ix->list_off, n, D, delta_d, ix->data,
+    BUILD_TRY(launch_pack(storage, P ? rot : src, ix->ids, ix->list_of_pos, ix->list_off, n, D, delta_d, ix->b1, ix->data,
                           ix->rows32, stream), "pack lists");
     const float *csrc = centroids;
     if (metric == ADS_METRIC_COSINE) {
@@ -651,6 +662,7 @@ extern "C" ads_status ads_index_info(const ads_index *ix, ads_index_desc *info) 
     info->storage = ix->storage;
     info->has_fp32_copy = ix->rows32 != nullptr;
     info->rotated = ix->P != nullptr;
+    info->a1_dims = ix->b1 * ix->dd;
     info->max_list = ix->max_list;
     info->metric = ix->metric;
     info->device_bytes = ix->bytes;
@@ -712,7 +724,7 @@ extern "C" ads_status ads_dco_batch(const ads_index *ix, const float *q_rot, con
     HIP_TRY(hipGetLastError(), "pending HIP error");
     const float r2 = r * r;
     HIP_TRY(launch_dco(ix->storage, ix->data, ix->rows32, source, ix->list_off, ix->list_of_pos, ix->pos_of,
-                       ix->n, ix->D, ix->dd, q_rot, cand, m, r2, (double)eps0, delta_d, method, pos_mask,
+                       ix->n, ix->D, ix->dd, ix->b1, q_rot, cand, m, r2, (double)eps0, delta_d, method, pos_mask,
                        dist, dims, reinterpret_cast<unsigned long long *>(stats), nullptr, stream),
             "dco_batch");
     return ADS_OK;
@@ -745,7 +757,7 @@ extern "C" ads_status ads_dco_batch_ip(const ads_index *ix, const float *q, cons
     IpArgs ipa{ix->norms, qnorm, r};
     if (e == hipSuccess)
         e = launch_dco(ix->storage, ix->data, ix->rows32, 0, ix->list_off, ix->list_of_pos, ix->pos_of, ix->n, D,
-                       ix->dd, qr, cand, m, 0.f, (double)eps0, delta_d, method, pos_mask, ip, dims,
+                       ix->dd, ix->b1, qr, cand, m, 0.f, (double)eps0, delta_d, method, pos_mask, ip, dims,
                        reinterpret_cast<unsigned long long *>(stats), &ipa, stream);
     (void)hipFreeAsync(scr, stream);
     if (e != hipSuccess) return hip_fail(e, "dco_batch_ip");
@@ -888,6 +900,7 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
         a.kcap = L.kcap;
         a.D = D;
         a.nb = ix->nb;
+        a.b1 = ix->b1;
         // automatic: smaller blocks make the register-dense phase cheaper per
         // test, so it is kept longer (measured best on the D = 960 workload)
         a.dense_frac = g_tune.dense_frac > 0.f ? g_tune.dense_frac : (ix->dd <= 16 ? 0.25f : 0.125f);

@@ -27,6 +27,20 @@ constexpr uint64_t KEY_NONE = ~0ull;
 constexpr int KCAP_LIMIT = 512;
 
 // ---------------------------------------------------------------------------
+// Stored layout of a list (IVF++, Section 5.2).  The first b1 blocks of dd
+// coordinates of all the list's vectors are stored block by block
+// ([block][vector][dd], the array A1 of the paper, read by the dense phase a
+// tile at a time); the remaining D - b1 dd coordinates are stored vector by
+// vector ([vector][D - b1 dd], the array A2, so the later blocks of one
+// candidate are contiguous).  Element offset of block b of vector v within
+// the list's slice of nl * D elements:
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ int64_t layout_offset(int64_t nl, int64_t v, int b, int dd, int b1, int D) {
+    return b < b1 ? (int64_t)b * nl * dd + v * dd
+                  : nl * (int64_t)b1 * dd + v * (int64_t)(D - b1 * dd) + (int64_t)(b - b1) * dd;
+}
+
+// ---------------------------------------------------------------------------
 // Test coefficients.  For a DCO that has sampled d of D coordinates with
 // partial sum S_d, ADSampling rejects dis <= r when
 //     sqrt(D/d * S_d) > (1 + eps0/sqrt(d)) * r

@@ -11,7 +11,7 @@ template <int DT>
 __global__ __launch_bounds__(ADS_WG) void dco_kernel(
     const void *__restrict__ data, const float *__restrict__ rows32, int source,
     const int64_t *__restrict__ list_off, const int32_t *__restrict__ list_of_pos,
-    const int32_t *__restrict__ pos_of, int64_t n, int D, int dd, const float *__restrict__ q,
+    const int32_t *__restrict__ pos_of, int64_t n, int D, int dd, int b1, const float *__restrict__ q,
     const int64_t *__restrict__ cand, int64_t m, float r2, double eps0, int step, int method,
     uint8_t *__restrict__ mask, float *__restrict__ dist, int32_t *__restrict__ dims,
     unsigned long long *stats, IpArgs ipa) {
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(ADS_WG) void dco_kernel(
                 if (source) {
                     o = rows32[p * D + t];
                 } else {
-                    o = load_one<DT>(data, off * D + (int64_t)b * nl * dd + v * dd + k);
+                    o = load_one<DT>(data, off * D + layout_offset(nl, v, b, dd, b1, D) + k);
                 }
                 float df = o - q[t];
                 pb = __fmaf_rn(df, df, pb);
@@ -115,7 +115,7 @@ template <int DT>
 __global__ __launch_bounds__(ADS_WG) void pack_kernel(
     const float *__restrict__ rot, const int32_t *__restrict__ ids,
     const int32_t *__restrict__ list_of_pos, const int64_t *__restrict__ list_off, int64_t n, int D,
-    int dd, void *__restrict__ data, float *__restrict__ rows32) {
+    int dd, int b1, void *__restrict__ data, float *__restrict__ rows32) {
     const int G = D / 4;
     const int64_t tot = n * G;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot;
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(ADS_WG) void pack_kernel(
         const int64_t nl = list_off[l + 1] - off;
         const int64_t v = p - off;
         const int b = t / dd, k = t - b * dd;
-        const int64_t dst = off * D + (int64_t)b * nl * dd + v * dd + k;
+        const int64_t dst = off * D + layout_offset(nl, v, b, dd, b1, D) + k;
         const float vv[4] = {val.x, val.y, val.z, val.w};
         if constexpr (DT == ADS_F32) {
             *reinterpret_cast<float4 *>(reinterpret_cast<float *>(data) + dst) = val;
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(ADS_WG) void row_norms_kernel(const float *x, int64
 
 hipError_t launch_dco(int dtype, const void *data, const float *rows32, int source,
                       const int64_t *list_off, const int32_t *list_of_pos, const int32_t *pos_of,
-                      int64_t n, int D, int dd_layout, const float *q, const int64_t *cand,
+                      int64_t n, int D, int dd_layout, int b1, const float *q, const int64_t *cand,
                       int64_t m, float r2, double eps0, int step, int method, uint8_t *mask,
                       float *dist, int32_t *dims, unsigned long long *stats, const IpArgs *ip,
                       hipStream_t s) {
@@ -188,17 +188,17 @@ hipError_t launch_dco(int dtype, const void *data, const float *rows32, int sour
     switch (dtype) {
         case ADS_F32:
             hipLaunchKernelGGL(dco_kernel<ADS_F32>, dim3(grid), dim3(ADS_WG), 0, s, data, rows32, source,
-                               list_off, list_of_pos, pos_of, n, D, dd_layout, q, cand, m, r2, eps0,
+                               list_off, list_of_pos, pos_of, n, D, dd_layout, b1, q, cand, m, r2, eps0,
                                step, method, mask, dist, dims, stats, ipa);
             break;
         case ADS_BF16:
             hipLaunchKernelGGL(dco_kernel<ADS_BF16>, dim3(grid), dim3(ADS_WG), 0, s, data, rows32, source,
-                               list_off, list_of_pos, pos_of, n, D, dd_layout, q, cand, m, r2, eps0,
+                               list_off, list_of_pos, pos_of, n, D, dd_layout, b1, q, cand, m, r2, eps0,
                                step, method, mask, dist, dims, stats, ipa);
             break;
         case ADS_F16:
             hipLaunchKernelGGL(dco_kernel<ADS_F16>, dim3(grid), dim3(ADS_WG), 0, s, data, rows32, source,
-                               list_off, list_of_pos, pos_of, n, D, dd_layout, q, cand, m, r2, eps0,
+                               list_off, list_of_pos, pos_of, n, D, dd_layout, b1, q, cand, m, r2, eps0,
                                step, method, mask, dist, dims, stats, ipa);
             break;
         default:
@@ -208,7 +208,7 @@ hipError_t launch_dco(int dtype, const void *data, const float *rows32, int sour
 }
 
 hipError_t launch_pack(int dtype, const float *rot, const int32_t *ids, const int32_t *list_of_pos,
-                       const int64_t *list_off, int64_t n, int D, int dd, void *data,
+                       const int64_t *list_off, int64_t n, int D, int dd, int b1, void *data,
                        float *rows32, hipStream_t s) {
     const int64_t tot = n * (D / 4);
     int64_t g = (tot + ADS_WG - 1) / ADS_WG;
@@ -216,15 +216,15 @@ hipError_t launch_pack(int dtype, const float *rot, const int32_t *ids, const in
     switch (dtype) {
         case ADS_F32:
             hipLaunchKernelGGL(pack_kernel<ADS_F32>, dim3(grid), dim3(ADS_WG), 0, s, rot, ids, list_of_pos,
-                               list_off, n, D, dd, data, rows32);
+                               list_off, n, D, dd, b1, data, rows32);
             break;
         case ADS_BF16:
             hipLaunchKernelGGL(pack_kernel<ADS_BF16>, dim3(grid), dim3(ADS_WG), 0, s, rot, ids, list_of_pos,
-                               list_off, n, D, dd, data, rows32);
+                               list_off, n, D, dd, b1, data, rows32);
             break;
         case ADS_F16:
             hipLaunchKernelGGL(pack_kernel<ADS_F16>, dim3(grid), dim3(ADS_WG), 0, s, rot, ids, list_of_pos,
-                               list_off, n, D, dd, data, rows32);
+                               list_off, n, D, dd, b1, data, rows32);
             break;
         default:
             return hipErrorInvalidValue;

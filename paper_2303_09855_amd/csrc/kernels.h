@@ -23,6 +23,7 @@ struct ScanArgs {
     double eps0;
     int method;
     int nprobe_max, kcap, D, nb;
+    int b1;                 // blocks of the list-major region of the layout (layout_offset)
     float dense_frac;       // pairs alive at or below this fraction (<= 0.25) switch to the pair list
     int round_tiles;        // 64-vector tiles per threshold update (4 in the first sweeps, else 1)
 };
@@ -46,7 +47,7 @@ struct IpArgs {
 
 hipError_t launch_dco(int dtype, const void *data, const float *rows32, int source,
                       const int64_t *list_off, const int32_t *list_of_pos, const int32_t *pos_of,
-                      int64_t n, int D, int dd_layout, const float *q, const int64_t *cand,
+                      int64_t n, int D, int dd_layout, int b1, const float *q, const int64_t *cand,
                       int64_t m, float r2, double eps0, int step, int method, uint8_t *mask,
                       float *dist, int32_t *dims, unsigned long long *stats, const IpArgs *ip,
                       hipStream_t s);
@@ -54,7 +55,7 @@ hipError_t launch_dco(int dtype, const void *data, const float *rows32, int sour
 hipError_t launch_normalize(const float *x, int64_t n, int D, float *out, float *norms, hipStream_t s);
 
 hipError_t launch_pack(int dtype, const float *rot, const int32_t *ids, const int32_t *list_of_pos,
-                       const int64_t *list_off, int64_t n, int D, int dd, void *data,
+                       const int64_t *list_off, int64_t n, int D, int dd, int b1, void *data,
                        float *rows32, hipStream_t s);
 
 hipError_t launch_row_norms(const float *x, int64_t n, int D, float *out, hipStream_t s);

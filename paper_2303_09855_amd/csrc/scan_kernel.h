@@ -226,7 +226,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(PF ? 2 :
             if (PF && tile_pairs > 0) {
                 float4 qv[QPL];
                 fetch_q(0, qv);
-                if ((amany >> lane) & 1ull) load_elems<DT, DD>(lbase + ((int64_t)v * DD) * EB, o);
+                if ((amany >> lane) & 1ull) load_elems<DT, DD>(lbase + layout_offset(nl, v, 0, DD, a.b1, D) * EB, o);
                 store_q(qv, sm.qs[w][0]);
             }
             for (; tile_pairs > 0 && b < nb; ++b) {
@@ -235,9 +235,9 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(PF ? 2 :
                 if constexpr (PF) {
                     const int bn = b + 1 < nb ? b + 1 : b;
                     fetch_q(bn, qv1);
-                    if ((amany >> lane) & 1ull) load_elems<DT, DD>(lbase + ((int64_t)bn * nl * DD + (int64_t)v * DD) * EB, o1);
+                    if ((amany >> lane) & 1ull) load_elems<DT, DD>(lbase + layout_offset(nl, v, bn, DD, a.b1, D) * EB, o1);
                 } else {
-                    if ((amany >> lane) & 1ull) load_elems<DT, DD>(lbase + ((int64_t)b * nl * DD + (int64_t)v * DD) * EB, o);
+                    if ((amany >> lane) & 1ull) load_elems<DT, DD>(lbase + layout_offset(nl, v, b, DD, a.b1, D) * EB, o);
                     fetch_q(b, qv1);
                     store_q(qv1, sm.qs[w][0]);
                 }
@@ -359,6 +359,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(PF ? 2 :
                 ctx.coef = coef;
                 ctx.D = D;
                 ctx.nb = nb;
+                ctx.b1 = a.b1;
                 const int32_t *tids = a.ids + off + vc;
                 uint64_t(*pos)[64] = sm.pos[w];
                 auto sink = [=](int jj, float s, int vv) {

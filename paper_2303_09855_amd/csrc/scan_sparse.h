@@ -92,7 +92,7 @@ struct SparseCtx {
     const int *qidx;              // [QW] query rows of the unit's slots (LDS)
     const float *r2s;             // [QW] thresholds (LDS)
     const float *coef;            // [nb] test coefficients (LDS)
-    int D, nb;
+    int D, nb, b1;
 };
 
 struct SparseOut {
@@ -133,7 +133,7 @@ __device__ __forceinline__ SparseOut sparse_run(const SparseCtx &c, uint64_t *li
             const bool bv = pv && blk < nb;
             float part = 0.f;
             if (bv) {
-                const unsigned char *op = c.lbase + ((int64_t)blk * c.nl * DD + (int64_t)(c.vc + vv) * DD) * EB;
+                const unsigned char *op = c.lbase + layout_offset(c.nl, c.vc + vv, blk, DD, c.b1, D) * EB;
                 part = block_partial<DT, DD>(op, c.qrot + (int64_t)c.qidx[jj] * D + blk * DD, 0.f);
             }
             // S after each block, added in block order (the canonical order,
