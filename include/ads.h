@@ -371,8 +371,7 @@ ads_status ads_plan_free(ads_plan *plan);
 typedef struct {
     float dense_frac;         /* (0, 0.25]: a 64-vector tile leaves the register-dense
                                  phase once at most this fraction of its (vector, query)
-                                 pairs is alive; 0 = automatic (0.25 for delta_d <= 16,
-                                 0.125 otherwise).  Default 0. */
+                                 pairs is alive; 0 = automatic (0.125).  Default 0. */
     int32_t queries_per_unit; /* 1, 2, 4, 8 or 16 queries per work unit; 0 = the largest
                                  power of two up to 8 whose KNN sets fit in 4 KB of LDS.
                                  Default 0. */

@@ -901,9 +901,9 @@ extern "C" ads_status ads_search(const ads_index *ix, const float *q, int32_t nq
         a.D = D;
         a.nb = ix->nb;
         a.b1 = ix->b1;
-        // automatic: smaller blocks make the register-dense phase cheaper per
-        // test, so it is kept longer (measured best on the D = 960 workload)
-        a.dense_frac = g_tune.dense_frac > 0.f ? g_tune.dense_frac : (ix->dd <= 16 ? 0.25f : 0.125f);
+        // automatic: hand over at 1/8 of the tile's pairs alive (measured best on
+        // the D = 960 workload with the IVF++ layout, for block widths 16 and 32)
+        a.dense_frac = g_tune.dense_frac > 0.f ? g_tune.dense_frac : 0.125f;
         a.round_tiles = s < WIDE_SWEEPS ? 4 : 1;
         // persistent grid: 8 XCD lanes x P workgroups, P bounded by the units of the sweep
         const int64_t pairs = (int64_t)nq * (rb - ra);
