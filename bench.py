@@ -62,11 +62,12 @@ def parse():
     ap.add_argument("--no-fds", action="store_true")
     ap.add_argument("--no-pds", action="store_true",
                     help="skip the PDScanning leg (IVF** on an unrotated index)")
-    ap.add_argument("--mode", default="search", choices=["search", "serve", "verify"],
+    ap.add_argument("--mode", default="search", choices=["search", "serve", "verify", "batched"],
                     help="search: the throughput benchmark (default); serve: the continuous-"
                          "batching request loop at Poisson arrival rates; verify: the fixed-"
                          "threshold failure-rate / dims sweep over eps0 and the linear-scan "
-                         "feasibility run")
+                         "feasibility run; batched: one captured search per batch with "
+                         "per-query K in {10, 100} and nprobe uniform on [8, 128]")
     ap.add_argument("--verify-queries", type=int, default=20, help="verify mode: queries")
     ap.add_argument("--verify-n", type=int, default=200_000,
                     help="verify mode: base vectors of the linear scans (the first n of the workload)")
@@ -208,6 +209,8 @@ def main() -> int:
 
     if args.mode == "serve":
         return serve(args, w, ix, q, gt, x)
+    if args.mode == "batched":
+        return batched(args, w, ix, q, x)
     if args.mode == "verify":
         ix.free()
         return verify(args, w, x, q, G)
@@ -257,7 +260,8 @@ def main() -> int:
     flops = 3.0 * dims  # one subtract and one fused multiply-add per sampled coordinate
     achieved_tflops = flops / (scan_ms_step * 1e-3) / 1e12
     scan_kernel = "scan_kernel"
-    traffic = scan_traffic_from_profile(scan_kernel)
+    traffic = scan_traffic_from_profile(
+        scan_kernel, profiled_config(w, p_ads, K, args.delta_d, args.eps0, args.storage, args.tune))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -344,6 +348,66 @@ def serve(args, w, ix, q, gt, x):
                                    f"batches <= {args.max_batch}, 3 streams"},
             "rates": out}
     print(json.dumps(line), flush=True)
+    ix.free()
+    return 0
+
+
+def batched(args, w, ix, q, x):
+    """One HIP-graph launch per batch of uneven queries: per-query K in {10, 100}
+    and nprobe uniform on [8, 128] (ADSampling, the same eps0); QPS of graph
+    replays and of the eager call, recall@K against the exact K nearest."""
+    import torch
+
+    import oracle
+    import paper_2303_09855_amd as ads
+    import synthdata as sd
+    Ks, Ps = sd.uneven_draws(w)
+    kmax, pmax = int(Ks.max()), int(Ps.max())
+    _, gt = oracle.brute_knn(x, q, kmax)
+    plan = ads.Plan(ix, w.nq, kmax, pmax, eps0=args.eps0)
+    plan.q.copy_(torch.as_tensor(q))
+    plan.K.copy_(torch.as_tensor(Ks))
+    plan.nprobe.copy_(torch.as_tensor(Ps))
+    torch.cuda.synchronize()
+    plan.launch()
+    torch.cuda.synchronize()
+    ids = plan.ids.cpu().numpy()
+    ex = exact_for(x, q, ids)
+    rec = oracle.recall(ids, ex, gt, Ks)
+    qd = torch.as_tensor(q).cuda()
+    Kd, Pd = torch.as_tensor(Ks).cuda(), torch.as_tensor(Ps).cuda()
+
+    def clock(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3 / args.steps
+
+    ms_graph = clock(plan.launch)
+    ms_eager = clock(lambda: ads.search(ix, qd, kmax, pmax, eps0=args.eps0, K=Kd, nprobe=Pd))
+    st = torch.zeros(ads.NSTATS, dtype=torch.int64, device="cuda")
+    ads.search(ix, qd, kmax, pmax, eps0=args.eps0, K=Kd, nprobe=Pd, stats=st)
+    torch.cuda.synchronize()
+    stv = st.cpu().numpy()
+    log(f"batched: graph {ms_graph:.3f} ms, eager {ms_eager:.3f} ms per {w.nq} queries, "
+        f"recall {rec:.4f}")
+    line = {"metric": "QPS of uneven batches (per-query K and nprobe), one graph launch per batch",
+            "value": round(w.nq / (ms_graph / 1e3), 1), "unit": "queries/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_graph, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": f"{w.name}: N={w.n}, D={w.D}, {w.nq} queries, nlist={w.nlist}, "
+                                   f"K in {{10,100}}, nprobe U[8,128], delta_d={args.delta_d}, "
+                                   f"eps0={args.eps0}"},
+            "eager_ms_per_step": round(ms_eager, 4), "recall_at_K": round(rec, 4),
+            "dcos_per_s": round(float(stv[ads.STAT_DCOS]) / (ms_graph / 1e3), 1),
+            "dims_ratio": round(float(stv[ads.STAT_DIMS]) / max(1.0, float(stv[ads.STAT_DCOS]) * w.D), 5)}
+    print(json.dumps(line), flush=True)
+    plan.free()
     ix.free()
     return 0
 
@@ -439,9 +503,16 @@ def scan_source_sha(kernel: str = "scan_kernel") -> str:
     return h.hexdigest()
 
 
-def scan_traffic_from_profile(kernel: str = "scan_kernel"):
+def profiled_config(w, nprobe, K, delta_d, eps0, storage, tune) -> str:
+    """The key naming the search configuration a counter summary was taken on."""
+    return (f"{w.name} n={w.n} nq={w.nq} nprobe={nprobe} K={K} delta_d={delta_d} eps0={eps0} "
+            f"storage={storage} tune={tune or '-'}")
+
+
+def scan_traffic_from_profile(kernel: str = "scan_kernel", config: str = ""):
     """HBM bytes per scan launch from the committed counter summary, or None
-    when the scan kernel sources changed since the counters were taken."""
+    when the scan kernel sources changed since the counters were taken or the
+    summary was taken on another search configuration."""
     prof = os.path.join(ROOT, "profiles", f"{kernel}_ivf_d960_counters.txt")
     try:
         sha = scan_source_sha(kernel)
@@ -451,6 +522,8 @@ def scan_traffic_from_profile(kernel: str = "scan_kernel"):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
         if fields.get("scan_source_sha256") != sha:
+            return None
+        if fields.get("profiled_config") != config:
             return None
         return float(fields["hbm_bytes_per_launch"])
     except (OSError, KeyError, ValueError):

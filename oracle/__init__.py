@@ -49,6 +49,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _BUILD = os.path.join(_HERE, "_build")
 _SO = os.path.join(_BUILD, "libads_oracle.so")
 _SRC = os.path.join(_HERE, "ads_oracle.c")
+_SRC_HNSW = os.path.join(_HERE, "hnsw_oracle.c")
+SOURCES = (_SRC, _SRC_HNSW)
 
 METHOD_ADS, METHOD_FDS, METHOD_PDS = 0, 1, 2
 
@@ -61,7 +63,7 @@ def build() -> str:
     """Compile the C part with gcc (always recompiles)."""
     os.makedirs(_BUILD, exist_ok=True)
     tmp = _SO + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC,
+    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall", "-o", tmp, *SOURCES,
            "-lm", "-lpthread"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _SO)
@@ -103,6 +105,15 @@ def bind(lib):
                                    i32p, ctypes.c_int, i32p, ctypes.c_int, ctypes.c_double,
                                    ctypes.c_int, ctypes.c_int, i64p, dp, i64p, ctypes.c_int]
     lib.orc_ivf_search.restype = ctypes.c_int
+    lib.orc_hnsw_search.argtypes = [dp, ctypes.c_int64, ctypes.c_int, dp, ctypes.c_int, i32p, i32p,
+                                    ctypes.c_int, i64p, i32p, ctypes.c_int, ctypes.c_int32,
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                    i64p, dp, i64p, ctypes.c_int]
+    lib.orc_hnsw_search.restype = ctypes.c_int
+    lib.orc_hnsw_dco.argtypes = [dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_int, ctypes.c_int, ctypes.c_double, ip, dp, dp, ip]
+    lib.orc_hnsw_dco.restype = ctypes.c_int
     return lib
 
 
@@ -379,6 +390,72 @@ def ivf_search(base_rot: np.ndarray, q_rot: np.ndarray, list_off: np.ndarray,
     if rc != 0:
         raise MemoryError("oracle ivf_search failed to allocate")
     return out_ids, out_dist, stats
+
+
+# ---------------------------------------------------------------------------
+# Section 2.2.1 / Section 4 / Section 5.1: graph search (HNSW, HNSW+, HNSW++)
+# ---------------------------------------------------------------------------
+
+HNSW_PLUS, HNSW_PLAIN, HNSW_PP = 0, 1, 2
+
+
+def hnsw_dco(o: np.ndarray, q: np.ndarray, r: float, eps0: float, delta_d: int,
+             method: int = METHOD_ADS, rel: float = 0.0):
+    """One DCO as the graph search runs it (Algorithm 1, or FDScanning with
+    ``method`` = METHOD_FDS): (positive, dims, exact distance or inf, observed
+    distance when it stopped, band flag)."""
+    lib = _load()
+    o = np.ascontiguousarray(o, dtype=np.float64)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    dims = ctypes.c_int()
+    dis = ctypes.c_double()
+    obs = ctypes.c_double()
+    band = ctypes.c_int()
+    pos = lib.orc_hnsw_dco(_p(o, ctypes.c_double), _p(q, ctypes.c_double), o.shape[0], float(r),
+                           float(eps0), int(delta_d), int(method), float(rel), ctypes.byref(dims),
+                           ctypes.byref(dis), ctypes.byref(obs), ctypes.byref(band))
+    return bool(pos), dims.value, dis.value, obs.value, bool(band.value)
+
+
+def hnsw_search(base_rot: np.ndarray, q_rot: np.ndarray, graph, K: int, nef: int,
+                eps0: float = 2.1, delta_d: int = 32, variant: int = HNSW_PLUS,
+                rel: float = 1e-6, rel_exact: float = 0.0, threads: int = 0):
+    """Graph search on transformed vectors: HNSW (Section 2.2.1, FDScanning
+    DCOs), HNSW+ (Section 4, Algorithm 1 as the DCO) or HNSW++ (Section 5.1,
+    R1 of K exact distances for the answer and the DCO threshold, R2 of N_ef
+    observed distances for the beam).  ``graph`` carries levels, adj0, up_off,
+    up_adj, entry, max_level, M and M0 (the format of the graph input).
+
+    Returns (ids [nq, K] int64, distances [nq, K] float64, stats [nq, 4] int64:
+    DCOs, sampled dims, layer-0 expansions, band flag).  The band flag marks a
+    query one of whose decisions lies within ``rel`` of its boundary (or whose
+    new key lies within ``rel`` of a key it is ordered against; ``rel_exact``
+    for two exact distances), where rounding could change the path."""
+    lib = _load()
+    base = np.ascontiguousarray(base_rot, dtype=np.float64)
+    q = np.ascontiguousarray(np.atleast_2d(q_rot), dtype=np.float64)
+    n, D = base.shape
+    nq = q.shape[0]
+    levels = np.ascontiguousarray(graph.levels, dtype=np.int32)
+    adj0 = np.ascontiguousarray(graph.adj0, dtype=np.int32)
+    up_off = np.ascontiguousarray(graph.up_off, dtype=np.int64)
+    up_adj = np.ascontiguousarray(graph.up_adj, dtype=np.int32)
+    ids = np.empty((nq, K), dtype=np.int64)
+    dist = np.empty((nq, K), dtype=np.float64)
+    stats = np.zeros((nq, 4), dtype=np.int64)
+    if threads <= 0:
+        threads = min(16, os.cpu_count() or 1)
+    st = lib.orc_hnsw_search(_p(base, ctypes.c_double), n, D, _p(q, ctypes.c_double), nq,
+                             _p(levels, ctypes.c_int32), _p(adj0, ctypes.c_int32),
+                             adj0.shape[1], _p(up_off, ctypes.c_int64),
+                             _p(up_adj, ctypes.c_int32), up_adj.shape[1], int(graph.entry),
+                             int(graph.max_level), int(K), int(nef), float(eps0), int(delta_d),
+                             int(variant), float(rel), float(rel_exact),
+                             _p(ids, ctypes.c_int64), _p(dist, ctypes.c_double),
+                             _p(stats, ctypes.c_int64), int(threads))
+    if st != 0:
+        raise ValueError("oracle hnsw_search: bad arguments or allocation failure")
+    return ids, dist, stats
 
 
 # ---------------------------------------------------------------------------

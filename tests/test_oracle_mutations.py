@@ -20,6 +20,7 @@ import oracle
 import test_oracle_pins as pins
 
 SRC = open(os.path.join(os.path.dirname(oracle.__file__), "ads_oracle.c")).read()
+HNSW_SRC = open(os.path.join(os.path.dirname(oracle.__file__), "hnsw_oracle.c")).read()
 
 
 def _in_function(fn, old, new):
@@ -105,19 +106,85 @@ def _built():
     oracle.build()
 
 
-@pytest.mark.parametrize("name", sorted(C_MUTANTS))
-def test_planted_c_mistake_fails_a_pin(name, tmp_path):
-    src = tmp_path / "mutant.c"
-    src.write_text(C_MUTANTS[name]())
+def _with_library(tmp_path, ads_src, hnsw_src, pins_fn):
+    a = tmp_path / "mutant_ads.c"
+    h = tmp_path / "mutant_hnsw.c"
+    a.write_text(ads_src)
+    h.write_text(hnsw_src)
     so = tmp_path / "libmutant.so"
-    subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", str(so), str(src), "-lm",
-                    "-lpthread"], check=True)
+    subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", str(so), str(a), str(h),
+                    "-lm", "-lpthread"], check=True)
     saved = oracle._load()
     oracle._lib = oracle.bind(ctypes.CDLL(str(so)))
     try:
-        failed = _failing_pins()
+        return pins_fn()
     finally:
         oracle._lib = saved
+
+
+@pytest.mark.parametrize("name", sorted(C_MUTANTS))
+def test_planted_c_mistake_fails_a_pin(name, tmp_path):
+    failed = _with_library(tmp_path, C_MUTANTS[name](), HNSW_SRC, _failing_pins)
+    assert failed, f"mutant {name} passed every pin"
+
+
+def _hnsw_in_function(fn, old, new):
+    start = HNSW_SRC.index(fn)
+    i = HNSW_SRC.index(old, start)
+    return HNSW_SRC[:i] + new + HNSW_SRC[i + len(old):]
+
+
+def _hnsw_once(old, new):
+    assert HNSW_SRC.count(old) == 1, old
+    return HNSW_SRC.replace(old, new)
+
+
+HNSW_MUTANTS = {
+    "pp_threshold_from_r2": lambda: _hnsw_once(
+        "double r = job->variant == 2 ? hset_threshold(&R1) : hset_threshold(&R);",
+        "double r = hset_threshold(&R);"),
+    "pp_rejected_kept_out_of_r2": lambda: _hnsw_once(
+        "hset_insert(&R, c.obs, v, exact);", "if (c.positive) hset_insert(&R, c.obs, v, exact);"),
+    "pp_observed_without_scale": lambda: _hnsw_in_function(
+        "static hdco h_dco", "double est = sqrt((double)D / (double)d * sq);",
+        "double est = d < D ? sqrt(sq) : sqrt((double)D / (double)d * sq);"),
+    "no_visited_set": lambda: _hnsw_once("if (visited[v]) continue;", ";"),
+    "upper_layers_ignore_threshold": lambda: _hnsw_once(
+        "hdco c = h_dco(job->base + v * D, q, D, dcur, job->eps0",
+        "hdco c = h_dco(job->base + v * D, q, D, INFINITY, job->eps0"),
+    "pop_farthest_unexpanded": lambda: _hnsw_once(
+        "int p = 0;\n        while (p < R.n && R.e[p].expanded) ++p;\n        if (p == R.n) break;",
+        "int p = R.n - 1;\n        while (p >= 0 && R.e[p].expanded) --p;\n        if (p < 0) break;"),
+    "ties_to_higher_id": lambda: _hnsw_once(
+        "return ka < kb || (ka == kb && ia < ib);", "return ka < kb || (ka == kb && ia > ib);"),
+    "positive_strict": lambda: _hnsw_in_function(
+        "static hdco h_dco", "out.positive = est <= r;", "out.positive = est < r;"),
+    "threshold_before_full": lambda: _hnsw_once(
+        "return s->n < s->cap ? INFINITY : s->e[s->n - 1].key;",
+        "return s->n > 0 ? s->e[s->n - 1].key : INFINITY;"),
+    "evict_nearest": lambda: _hnsw_once(
+        "int last = s->n < s->cap ? s->n : s->cap - 1;",
+        "if (s->n == s->cap) { for (int i = 0; i + 1 < s->n; ++i) s->e[i] = s->e[i + 1]; s->n--; if (p > 0) p--; }\n    int last = s->n;"),
+}
+
+
+def _hnsw_pins():
+    import test_oracle_hnsw as hp
+    checks = [("hnsw_golden:" + c["name"], lambda c=c: hp.test_hnsw_golden_tiny(c))
+              for c in hp._tiny_cases()]
+    checks.append(("hnsw_dco", hp.test_hnsw_dco_is_algorithm_1))
+    failed = []
+    for name, fn in checks:
+        try:
+            fn()
+        except AssertionError:
+            failed.append(name)
+    return failed
+
+
+@pytest.mark.parametrize("name", sorted(HNSW_MUTANTS))
+def test_planted_graph_search_mistake_fails_a_pin(name, tmp_path):
+    failed = _with_library(tmp_path, SRC, HNSW_MUTANTS[name](), _hnsw_pins)
     assert failed, f"mutant {name} passed every pin"
 
 
