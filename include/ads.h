@@ -419,6 +419,84 @@ ads_status ads_profile_enable(int32_t on);
  */
 ads_status ads_profile_collect(double *ms, int64_t *launches);
 
+/* --------------------------------------------------------------------------
+ * Graph search: HNSW (Section 2.2.1), HNSW+ (Section 4) and HNSW++ (Section 5.1)
+ * -------------------------------------------------------------------------- */
+
+typedef struct ads_hnsw ads_hnsw;   /* opaque, device-resident, library-owned */
+
+typedef enum {
+    ADS_HNSW_PLUS = 0,   /* HNSW+: Algorithm 1 DCOs against R's largest distance */
+    ADS_HNSW_PLAIN = 1,  /* HNSW: full-dimension DCOs (FDScanning) */
+    ADS_HNSW_PP = 2      /* HNSW++: R1 (K exact distances) gives the threshold and the
+                            answer, R2 (N_ef observed distances) drives the beam */
+} ads_hnsw_variant;
+
+/*
+ * ads_hnsw_create -- builds a graph index on the device from a graph given on
+ * the host (the HNSW index phase, Section 2.2.1; the method leaves the graph
+ * construction unchanged, so the caller supplies it, e.g. from hnswlib or the
+ * seeded builder of the test inputs).
+ *
+ *   base     device [n][D] float32 raw vectors, row-major.
+ *   P        device [D][D] float32 rotation (y = P x, Section 3.1), copied; NULL
+ *            stores the vectors unrotated (then only ADS_HNSW_PLAIN, or eps0 =
+ *            +inf, may search it).
+ *   levels   host [n] top layer of each vertex (>= 0).
+ *   adj0     host [n][M0] layer-0 neighbour ids in the order the search examines
+ *            them, -1 padded at the end of a row; no duplicates in a row.
+ *   up_off   host [n]: for a vertex with levels[v] >= 1, the row of up_adj
+ *            holding its layer-1 neighbours (its layer-l row is up_off[v] + l - 1);
+ *            ignored for levels[v] == 0.
+ *   up_adj   host [up_rows][M] upper-layer neighbour ids, -1 padded at the end;
+ *            a neighbour on layer l must have levels >= l.  NULL if up_rows == 0.
+ *   entry    the vertex the search starts from; levels[entry] must be the
+ *            largest level.
+ *   delta_d  coordinates per sampling step: 8, 16 or 32; D must be a multiple
+ *            of 32 and D / delta_d <= 128.  M0, M <= 32.
+ *
+ * Every id and row is checked on the host before anything is copied.
+ * Synchronises the stream.  Errors: ADS_EINVAL (with the offending vertex in
+ * ads_last_error), ADS_ENOMEM, ADS_EHIP.
+ */
+ads_status ads_hnsw_create(const float *base, int64_t n, int32_t D, const float *P,
+                           const int32_t *levels, const int32_t *adj0, int32_t M0,
+                           const int64_t *up_off, const int32_t *up_adj, int64_t up_rows,
+                           int32_t M, int32_t entry, int32_t delta_d, hipStream_t stream,
+                           ads_hnsw **out);
+
+/* ads_hnsw_workspace_size -- HOST: bytes of workspace ads_hnsw_search needs for
+ * nq queries (the transformed queries, the test coefficients and one visited
+ * bitmap of n bits per query); 0 for invalid arguments. */
+uint64_t ads_hnsw_workspace_size(const ads_hnsw *ix, int32_t nq);
+
+/*
+ * ads_hnsw_search -- graph search of nq queries, one answer of K per query.
+ *
+ *   q        device [nq][D] float32 raw queries (rotated inside).
+ *   K, nef   answer size and beam width N_ef (K <= nef for HNSW and HNSW+;
+ *            HNSW++ keeps R1 of K and R2 of nef); 1 <= K <= 256, nef <= 1024.
+ *   eps0     Algorithm 1's parameter (>= 0; +inf never rejects); ignored by
+ *            ADS_HNSW_PLAIN.
+ *   ids      device [nq][K] int64 out, ascending (distance, id); -1 padded.
+ *   dist     device [nq][K] float32 out, distances (not squared); +inf padded.
+ *   qstats   device [nq][3] int64 out: DCOs, sampled coordinates and layer-0
+ *            expansions of each query, or NULL.
+ *   stats    device [3] int64 accumulators of the same three counts, or NULL.
+ *   workspace device, 256-byte aligned, >= ads_hnsw_workspace_size bytes, or
+ *            NULL to allocate it on the stream.
+ *
+ * Asynchronous on `stream`.  Ties are ordered by id, every set is keyed by
+ * (squared distance, id), and the search ends when every member of R (R2)
+ * has been expanded.  Errors: ADS_EINVAL, ADS_ENOMEM, ADS_EHIP.
+ */
+ads_status ads_hnsw_search(const ads_hnsw *ix, const float *q, int32_t nq, int32_t K, int32_t nef,
+                           float eps0, int32_t variant, int64_t *ids, float *dist, int64_t *qstats,
+                           int64_t *stats, void *workspace, hipStream_t stream);
+
+/* ads_hnsw_free -- releases the index (synchronises the device).  NULL is a no-op. */
+ads_status ads_hnsw_free(ads_hnsw *ix);
+
 /* ads_last_error -- thread-local message for the last failing call on this
  * thread ("" if none).  The pointer stays valid until the next call. */
 const char *ads_last_error(void);

@@ -74,10 +74,10 @@ typedef struct {
  * method 0: Algorithm 1 (ADSampling) with eps0 and delta_d; method 1:
  * FDScanning.  r may be +inf.  The band flag is set when, at a point where the
  * DCO compares with a finite boundary, the compared value lies within
- * rel * boundary of it.
+ * rel * boundary of it (rel_exact for the exact comparison at d = D).
  */
 static hdco h_dco(const double *o, const double *q, int D, double r, double eps0, int delta_d,
-                  int method, double rel)
+                  int method, double rel, double rel_exact)
 {
     hdco out;
     memset(&out, 0, sizeof(out));
@@ -106,7 +106,7 @@ static hdco h_dco(const double *o, const double *q, int D, double r, double eps0
             continue;                                   /* Case 2 */
         }
         /* Case 3: exact */
-        if (!isinf(r) && fabs(est - r) <= rel * r) out.band = 1;
+        if (!isinf(r) && rel_exact > 0.0 && fabs(est - r) <= rel_exact * r) out.band = 1;
         out.positive = est <= r;
         out.dims = D;
         out.dis = est;
@@ -221,7 +221,8 @@ static void hnsw_one_query(hnsw_job *job, int qi, uint8_t *visited, hent *rbuf, 
 
     /* entry vertex: full distance */
     int64_t cur = job->entry;
-    hdco c0 = h_dco(job->base + cur * D, q, D, INFINITY, job->eps0, job->delta_d, method, job->rel);
+    hdco c0 = h_dco(job->base + cur * D, q, D, INFINITY, job->eps0, job->delta_d, method, job->rel,
+                    job->rel_exact);
     double dcur = c0.dis;
     dcos += 1;
     dims += c0.dims;
@@ -234,7 +235,8 @@ static void hnsw_one_query(hnsw_job *job, int qi, uint8_t *visited, hent *rbuf, 
             const int32_t *row = job->up_adj + (job->up_off[cur] + (l - 1)) * (int64_t)job->M;
             for (int j = 0; j < job->M && row[j] >= 0; ++j) {
                 int64_t v = row[j];
-                hdco c = h_dco(job->base + v * D, q, D, dcur, job->eps0, job->delta_d, method, job->rel);
+                hdco c = h_dco(job->base + v * D, q, D, dcur, job->eps0, job->delta_d, method, job->rel,
+                               job->rel_exact);
                 dcos += 1;
                 dims += c.dims;
                 band |= c.band;
@@ -271,7 +273,8 @@ static void hnsw_one_query(hnsw_job *job, int qi, uint8_t *visited, hent *rbuf, 
             if (visited[v]) continue;
             visited[v] = 1;
             double r = job->variant == 2 ? hset_threshold(&R1) : hset_threshold(&R);
-            hdco c = h_dco(job->base + v * D, q, D, r, job->eps0, job->delta_d, method, job->rel);
+            hdco c = h_dco(job->base + v * D, q, D, r, job->eps0, job->delta_d, method, job->rel,
+                           job->rel_exact);
             dcos += 1;
             dims += c.dims;
             band |= c.band;
@@ -370,7 +373,7 @@ int orc_hnsw_search(const double *base, int64_t n, int D, const double *queries,
 int orc_hnsw_dco(const double *o, const double *q, int D, double r, double eps0, int delta_d,
                  int method, double rel, int *dims, double *dis, double *obs, int *band)
 {
-    hdco c = h_dco(o, q, D, r, eps0, delta_d, method, rel);
+    hdco c = h_dco(o, q, D, r, eps0, delta_d, method, rel, rel);
     *dims = c.dims;
     *dis = c.dis;
     *obs = c.obs;

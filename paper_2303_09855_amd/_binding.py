@@ -27,7 +27,9 @@ EXPORTED = [
     "ads_last_error", "ads_version", "ads_profile_enable", "ads_profile_collect",
     "ads_set_tuning", "ads_get_tuning", "ads_plan_create", "ads_plan_launch", "ads_plan_free",
     "ads_dco_batch_ip", "ads_search_noalloc", "ads_kmeans", "ads_build_ivf",
+    "ads_hnsw_create", "ads_hnsw_workspace_size", "ads_hnsw_search", "ads_hnsw_free",
 ]
+HNSW_PLUS, HNSW_PLAIN, HNSW_PP = 0, 1, 2
 NOALLOC_SCRATCH_BYTES = 256 << 20       # ADS_NOALLOC_SCRATCH_BYTES
 METRIC_L2, METRIC_COSINE = 0, 1
 PHASES = ["rotate", "probe", "group", "scan", "merge", "output"]
@@ -89,12 +91,19 @@ def load() -> ctypes.CDLL:
     lib.ads_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
     lib.ads_profile_enable.argtypes = [i32]
     lib.ads_profile_collect.argtypes = [vp, vp]
+    lib.ads_hnsw_create.argtypes = [vp, i64, i32, vp, vp, vp, i32, vp, vp, i64, i32, i32, i32, vp,
+                                    ctypes.POINTER(vp)]
+    lib.ads_hnsw_workspace_size.argtypes = [vp, i32]
+    lib.ads_hnsw_workspace_size.restype = ctypes.c_uint64
+    lib.ads_hnsw_search.argtypes = [vp, vp, i32, i32, i32, f32, i32, vp, vp, vp, vp, vp, vp]
+    lib.ads_hnsw_free.argtypes = [vp]
     lib.ads_last_error.restype = ctypes.c_char_p
     lib.ads_version.restype = ctypes.c_char_p
     for name in ["ads_make_rotation", "ads_rotate", "ads_ivf_build", "ads_index_info",
                  "ads_index_lists", "ads_index_free", "ads_dco_batch", "ads_search",
                  "ads_profile_enable", "ads_profile_collect", "ads_set_tuning", "ads_get_tuning",
-                 "ads_plan_create", "ads_plan_launch", "ads_plan_free", "ads_dco_batch_ip"]:
+                 "ads_plan_create", "ads_plan_launch", "ads_plan_free", "ads_dco_batch_ip",
+                 "ads_hnsw_create", "ads_hnsw_search", "ads_hnsw_free"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -220,6 +229,70 @@ def ivf_build(base, P, centroids, assign, delta_d: int = 32, storage: int = F32,
                                 _ptr(assign), int(delta_d), int(storage), int(bool(keep_fp32)),
                                 int(metric), _stream(), ctypes.byref(out)))
     return Index(out)
+
+
+class HnswIndex:
+    """Owning handle of an ads_hnsw graph index."""
+
+    def __init__(self, handle: ctypes.c_void_p, n: int, D: int):
+        self._h = handle
+        self.n, self.D = n, D
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise RuntimeError("graph index was freed")
+        return self._h
+
+    def free(self) -> None:
+        if self._h:
+            load().ads_hnsw_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def hnsw_create(base, P, graph, delta_d: int = 16) -> HnswIndex:
+    """ads_hnsw_create from a graph given on the host (``graph`` carries levels,
+    adj0, up_off, up_adj, entry, M).  P None stores the vectors unrotated."""
+    torch = _torch()
+    base = _dev(base, torch.float32)
+    P = _dev(P, torch.float32) if P is not None else None
+    n, D = base.shape
+    levels = np.ascontiguousarray(graph.levels, dtype=np.int32)
+    adj0 = np.ascontiguousarray(graph.adj0, dtype=np.int32)
+    up_off = np.ascontiguousarray(graph.up_off, dtype=np.int64)
+    up_adj = np.ascontiguousarray(graph.up_adj, dtype=np.int32)
+    rows = int(up_adj.shape[0]) if int(levels.max()) > 0 else 0
+    out = ctypes.c_void_p()
+    _check(load().ads_hnsw_create(_ptr(base), n, D, _ptr(P), levels.ctypes.data, adj0.ctypes.data,
+                                  int(adj0.shape[1]), up_off.ctypes.data, up_adj.ctypes.data, rows,
+                                  int(up_adj.shape[1]), int(graph.entry), int(delta_d), _stream(),
+                                  ctypes.byref(out)))
+    return HnswIndex(out, n, D)
+
+
+def hnsw_search(index: HnswIndex, q, K: int, nef: int, eps0: float = 2.1,
+                variant: int = HNSW_PLUS, qstats=None, stats=None, workspace=None):
+    """ads_hnsw_search.  Returns (ids int64 [nq, K], dist float32 [nq, K])."""
+    torch = _torch()
+    q = _dev(q, torch.float32)
+    nq = q.shape[0]
+    ids = torch.empty((nq, K), dtype=torch.int64, device="cuda")
+    dist = torch.empty((nq, K), dtype=torch.float32, device="cuda")
+    e = math.inf if eps0 is None else float(eps0)
+    _check(load().ads_hnsw_search(index.handle, _ptr(q), nq, int(K), int(nef), e, int(variant),
+                                  _ptr(ids), _ptr(dist), _ptr(qstats), _ptr(stats), _ptr(workspace),
+                                  _stream()))
+    return ids, dist
+
+
+def hnsw_workspace_size(index: HnswIndex, nq: int) -> int:
+    return int(load().ads_hnsw_workspace_size(index.handle, nq))
 
 
 def kmeans(x, nlist: int, iters: int = 10, seed: int = 0):

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 OBJDIR = os.path.join(LIBDIR, "obj")
 LIB = os.path.join(LIBDIR, "libads.so")
-SOURCES = ["api.hip", "scan.hip", "gemm.hip", "dco.hip", "kmeans.hip"]
+SOURCES = ["api.hip", "scan.hip", "gemm.hip", "dco.hip", "kmeans.hip", "hnsw.hip"]
 SCAN_DTYPES = [0, 1, 2]          # ADS_F32, ADS_BF16, ADS_F16
 SCAN_WIDTHS = [8, 16, 32, 64]    # supported block widths of the stored layout
 

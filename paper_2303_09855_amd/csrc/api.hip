@@ -1107,6 +1107,243 @@ extern "C" ads_status ads_profile_collect(double *ms, int64_t *launches) {
     return st;
 }
 
+// ---------------------------------------------------------------------------
+// Graph search (Section 2.2.1, Section 4, Section 5.1)
+// ---------------------------------------------------------------------------
+
+struct ads_hnsw {
+    int64_t n = 0, up_rows = 0;
+    int D = 0, M0 = 0, M = 0, max_level = 0, entry = 0, dd = 0, nb = 0;
+    float *P = nullptr;          // NULL for unrotated vectors
+    float *data = nullptr;       // [n][D] transformed vectors
+    int32_t *adj0 = nullptr;     // [n][M0]
+    int64_t *up_off = nullptr;   // [n]
+    int32_t *up_adj = nullptr;   // [up_rows][M]
+    int64_t bytes = 0;
+};
+
+namespace {
+
+void free_hnsw(ads_hnsw *ix) {
+    if (!ix) return;
+    void *ptrs[] = {ix->P, ix->data, ix->adj0, ix->up_off, ix->up_adj};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    delete ix;
+}
+
+// One neighbour row: ids in [0, n), -1 only as padding at the end, no
+// duplicates, and (above layer 0) every neighbour present on `layer`.
+ads_status check_row(const int32_t *row, int width, int64_t n, const int32_t *levels, int layer,
+                     int64_t v, std::vector<int32_t> &tmp) {
+    tmp.clear();
+    bool pad = false;
+    for (int j = 0; j < width; ++j) {
+        int32_t u = row[j];
+        if (u < 0) {
+            if (u != -1) return fail(ADS_EINVAL, "vertex %lld layer %d: neighbour id %d", (long long)v, layer, u);
+            pad = true;
+            continue;
+        }
+        if (pad) return fail(ADS_EINVAL, "vertex %lld layer %d: id after -1 padding", (long long)v, layer);
+        if (u >= n) return fail(ADS_EINVAL, "vertex %lld layer %d: neighbour %d out of range", (long long)v, layer, u);
+        if (layer > 0 && levels[u] < layer)
+            return fail(ADS_EINVAL, "vertex %lld layer %d: neighbour %d is not on that layer", (long long)v, layer, u);
+        tmp.push_back(u);
+    }
+    std::sort(tmp.begin(), tmp.end());
+    if (std::adjacent_find(tmp.begin(), tmp.end()) != tmp.end())
+        return fail(ADS_EINVAL, "vertex %lld layer %d: duplicate neighbour", (long long)v, layer);
+    return ADS_OK;
+}
+
+}  // namespace
+
+extern "C" ads_status ads_hnsw_create(const float *base, int64_t n, int32_t D, const float *P,
+                                      const int32_t *levels, const int32_t *adj0, int32_t M0,
+                                      const int64_t *up_off, const int32_t *up_adj, int64_t up_rows,
+                                      int32_t M, int32_t entry, int32_t delta_d, hipStream_t stream,
+                                      ads_hnsw **out) {
+    if (!out) return fail(ADS_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    if (!base || !levels || !adj0 || !up_off) return fail(ADS_EINVAL, "base, levels, adj0 and up_off must not be NULL");
+    if (n < 1 || n >= INT32_MAX) return fail(ADS_EINVAL, "n must be in [1, 2^31 - 1) (got %lld)", (long long)n);
+    if (delta_d != 8 && delta_d != 16 && delta_d != 32)
+        return fail(ADS_EINVAL, "delta_d must be 8, 16 or 32 (got %d)", delta_d);
+    if (D < 32 || D % 32 || D / delta_d > HN_MAXBLOCKS)
+        return fail(ADS_EINVAL, "D must be a multiple of 32 with D / delta_d <= %d (got D = %d)", HN_MAXBLOCKS, D);
+    if (M0 < 1 || M0 > HN_MAXDEG) return fail(ADS_EINVAL, "M0 must be in [1, %d] (got %d)", HN_MAXDEG, M0);
+    if (up_rows < 0) return fail(ADS_EINVAL, "up_rows must be >= 0");
+    if (up_rows > 0 && (!up_adj || M < 1 || M > HN_MAXDEG))
+        return fail(ADS_EINVAL, "upper rows need up_adj and M in [1, %d]", HN_MAXDEG);
+    if (entry < 0 || entry >= n) return fail(ADS_EINVAL, "entry %d out of range", entry);
+    const int top = levels[entry];
+    std::vector<int32_t> tmp;
+    for (int64_t v = 0; v < n; ++v) {
+        const int lv = levels[v];
+        if (lv < 0 || lv > top)
+            return fail(ADS_EINVAL, "vertex %lld: level %d outside [0, level of the entry = %d]", (long long)v, lv, top);
+        ads_status st = check_row(adj0 + v * M0, M0, n, levels, 0, v, tmp);
+        if (st != ADS_OK) return st;
+        if (lv == 0) continue;
+        if (up_off[v] < 0 || up_off[v] + lv > up_rows)
+            return fail(ADS_EINVAL, "vertex %lld: upper rows [%lld, %lld) outside [0, %lld)", (long long)v,
+                        (long long)up_off[v], (long long)(up_off[v] + lv), (long long)up_rows);
+        for (int l = 1; l <= lv; ++l) {
+            st = check_row(up_adj + (up_off[v] + l - 1) * M, M, n, levels, l, v, tmp);
+            if (st != ADS_OK) return st;
+        }
+    }
+    HIP_TRY(hipGetLastError(), "pending HIP error");
+
+    ads_hnsw *ix = new ads_hnsw();
+    ix->n = n;
+    ix->D = D;
+    ix->M0 = M0;
+    ix->M = up_rows > 0 ? M : 1;
+    ix->max_level = top;
+    ix->entry = entry;
+    ix->dd = delta_d;
+    ix->nb = D / delta_d;
+    ix->up_rows = up_rows;
+    hipError_t e = hipSuccess;
+#define HNSW_TRY(expr, what)                                                             \
+    do {                                                                                 \
+        e = (expr);                                                                      \
+        if (e != hipSuccess) {                                                           \
+            free_hnsw(ix);                                                               \
+            return e == hipErrorOutOfMemory ? fail(ADS_ENOMEM, "%s: out of device memory", what) \
+                                            : hip_fail(e, what);                         \
+        }                                                                                \
+    } while (0)
+    HNSW_TRY(dmalloc(&ix->data, (size_t)n * D, &ix->bytes), "vectors");
+    HNSW_TRY(dmalloc(&ix->adj0, (size_t)n * M0, &ix->bytes), "layer-0 rows");
+    HNSW_TRY(dmalloc(&ix->up_off, (size_t)n, &ix->bytes), "upper offsets");
+    HNSW_TRY(dmalloc(&ix->up_adj, (size_t)(up_rows > 0 ? up_rows : 1) * ix->M, &ix->bytes), "upper rows");
+    if (P) {
+        HNSW_TRY(dmalloc(&ix->P, (size_t)D * D, &ix->bytes), "rotation");
+        HNSW_TRY(hipMemcpyAsync(ix->P, P, (size_t)D * D * 4, hipMemcpyDeviceToDevice, stream), "copy P");
+        HNSW_TRY(gemm_nt_f32(base, D, ix->P, D, ix->data, D, n, D, D, stream), "rotate vectors");
+    } else {
+        HNSW_TRY(hipMemcpyAsync(ix->data, base, (size_t)n * D * 4, hipMemcpyDeviceToDevice, stream), "copy vectors");
+    }
+    HNSW_TRY(hipMemcpyAsync(ix->adj0, adj0, (size_t)n * M0 * 4, hipMemcpyHostToDevice, stream), "copy layer 0");
+    std::vector<int64_t> off(up_off, up_off + n);
+    for (int64_t v = 0; v < n; ++v)
+        if (levels[v] == 0) off[v] = -1;
+    HNSW_TRY(hipMemcpyAsync(ix->up_off, off.data(), (size_t)n * 8, hipMemcpyHostToDevice, stream), "copy offsets");
+    if (up_rows > 0)
+        HNSW_TRY(hipMemcpyAsync(ix->up_adj, up_adj, (size_t)up_rows * M * 4, hipMemcpyHostToDevice, stream),
+                 "copy upper rows");
+    HNSW_TRY(hipStreamSynchronize(stream), "create");
+#undef HNSW_TRY
+    *out = ix;
+    return ADS_OK;
+}
+
+namespace {
+
+struct HnswLayout {
+    size_t off_qrot, off_coef, off_vis, total;
+    int64_t words;
+};
+
+HnswLayout hnsw_layout(const ads_hnsw *ix, int nq) {
+    HnswLayout L;
+    L.words = (ix->n + 31) / 32;
+    L.off_qrot = 0;
+    L.off_coef = align256((size_t)nq * ix->D * 4);
+    L.off_vis = L.off_coef + align256((size_t)ix->nb * 4);
+    L.total = L.off_vis + align256((size_t)nq * L.words * 4);
+    return L;
+}
+
+}  // namespace
+
+extern "C" uint64_t ads_hnsw_workspace_size(const ads_hnsw *ix, int32_t nq) {
+    if (!ix || nq < 0) return 0;
+    return (uint64_t)hnsw_layout(ix, nq).total;
+}
+
+extern "C" ads_status ads_hnsw_search(const ads_hnsw *ix, const float *q, int32_t nq, int32_t K, int32_t nef,
+                                      float eps0, int32_t variant, int64_t *ids, float *dist, int64_t *qstats,
+                                      int64_t *stats, void *workspace, hipStream_t stream) {
+    if (!ix) return fail(ADS_EINVAL, "index must not be NULL");
+    if (nq < 0) return fail(ADS_EINVAL, "nq must be >= 0");
+    if (variant < ADS_HNSW_PLUS || variant > ADS_HNSW_PP) return fail(ADS_EINVAL, "unknown variant %d", variant);
+    if (K < 1 || K > 256) return fail(ADS_EINVAL, "K must be in [1, 256] (got %d)", K);
+    if (nef < 1 || nef > 1024) return fail(ADS_EINVAL, "nef must be in [1, 1024] (got %d)", nef);
+    if (variant != ADS_HNSW_PP && nef < K) return fail(ADS_EINVAL, "nef (%d) must be >= K (%d)", nef, K);
+    if (!(eps0 >= 0.f)) return fail(ADS_EINVAL, "eps0 must be >= 0 (got %g)", (double)eps0);
+    if (!ix->P && variant != ADS_HNSW_PLAIN && !std::isinf(eps0))
+        return fail(ADS_EINVAL, "ADSampling needs a rotated index (created with P); this one stores unrotated vectors");
+    if (nq == 0) return ADS_OK;
+    if (!q || !ids || !dist) return fail(ADS_EINVAL, "q, ids and dist must not be NULL");
+    if (workspace && (reinterpret_cast<uintptr_t>(workspace) & 255u))
+        return fail(ADS_EINVAL, "workspace must be 256-byte aligned");
+    const size_t smem = hnsw_smem_bytes(ix->D, ix->nb, nef, K);
+    if (smem > 64 * 1024) return fail(ADS_EINVAL, "D, nef and K need %zu bytes of LDS (> 64 KiB)", smem);
+    HIP_TRY(hipGetLastError(), "pending HIP error");
+
+    const HnswLayout L = hnsw_layout(ix, nq);
+    unsigned char *ws = reinterpret_cast<unsigned char *>(workspace);
+    bool own = false;
+    if (!ws) {
+        hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&ws), L.total, stream);
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(ADS_ENOMEM, "workspace: out of device memory")
+                                                             : hip_fail(e, "workspace allocation");
+        own = true;
+    }
+    float *qrot = reinterpret_cast<float *>(ws + L.off_qrot);
+    float *coef = reinterpret_cast<float *>(ws + L.off_coef);
+    uint32_t *vis = reinterpret_cast<uint32_t *>(ws + L.off_vis);
+    auto done = [&](hipError_t err, const char *what) -> ads_status {
+        if (own) (void)hipFreeAsync(ws, stream);
+        return err == hipSuccess ? ADS_OK : hip_fail(err, what);
+    };
+    hipError_t e;
+    if (ix->P)
+        e = gemm_nt_f32(q, ix->D, ix->P, ix->D, qrot, ix->D, nq, ix->D, ix->D, stream);
+    else
+        e = hipMemcpyAsync(qrot, q, (size_t)nq * ix->D * 4, hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return done(e, "rotate queries");
+    const int method = variant == ADS_HNSW_PLAIN || std::isinf(eps0) ? ADS_METHOD_FDSCANNING : ADS_METHOD_ADSAMPLING;
+    e = launch_hnsw_setup(coef, ix->nb, ix->dd, ix->D, (double)eps0, method, vis, (int64_t)nq * L.words, stream);
+    if (e != hipSuccess) return done(e, "search setup");
+    HnswArgs a;
+    a.data = ix->data;
+    a.adj0 = ix->adj0;
+    a.up_off = ix->up_off;
+    a.up_adj = ix->up_adj;
+    a.qrot = qrot;
+    a.coef = coef;
+    a.visited = vis;
+    a.vis_words = L.words;
+    a.ids = ids;
+    a.dist = dist;
+    a.qstats = qstats;
+    a.stats = reinterpret_cast<unsigned long long *>(stats);
+    a.D = ix->D;
+    a.nb = ix->nb;
+    a.dd = ix->dd;
+    a.M0 = ix->M0;
+    a.M = ix->M;
+    a.entry = ix->entry;
+    a.max_level = ix->max_level;
+    a.K = K;
+    a.nef = nef;
+    a.variant = variant;
+    e = launch_hnsw_search(a, nq, stream);
+    return done(e, "graph search");
+}
+
+extern "C" ads_status ads_hnsw_free(ads_hnsw *ix) {
+    if (!ix) return ADS_OK;
+    (void)hipDeviceSynchronize();
+    free_hnsw(ix);
+    return ADS_OK;
+}
+
 extern "C" const char *ads_last_error(void) { return g_err.c_str(); }
 
 extern "C" const char *ads_version(void) { return "ads-mi355x 0.1.0 (gfx950)"; }

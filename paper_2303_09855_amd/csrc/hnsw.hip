@@ -1,0 +1,389 @@
+// Graph search with ADSampling DCOs: HNSW (Section 2.2.1, FDScanning DCOs),
+// HNSW+ (Section 4, Algorithm 1 as the DCO against the largest distance of the
+// result set R) and HNSW++ (Section 5.1: R1 of K exact distances supplies the
+// DCO threshold and the answer; R2 of N_ef observed distances drives the beam).
+//
+// One wave per query.  The search is a chain of dependent steps, so the
+// parallelism inside a query is the neighbour list of the vertex being
+// expanded: its not-yet-visited neighbours (up to 32) are DCO'd together, 8
+// lanes per neighbour and 4 neighbours per lane group in flight, against the
+// threshold that holds when the expansion starts, and the partial sum after
+// every block of delta_d coordinates is kept in LDS.  The sequential semantics
+// (the threshold may shrink after each insertion) are then replayed neighbour
+// by neighbour from those partial sums: a smaller threshold can only move a
+// rejection to an earlier block (the test compares S_d with coef(d) r^2), so
+// the stored sums always reach the block where the sequential DCO stops.  The
+// outcome, the sampled dimensions and the observed distance are exactly those
+// of the one-at-a-time loop over the same floating-point sums.
+//
+// Sets are sorted arrays of (squared distance, id) keys in LDS (lexicographic
+// order, so no two keys tie).  S is the set of R's (R2's) members not expanded
+// yet: with these keys an evicted member can never be expanded later, because
+// R's largest key only shrinks once R is full, so popping the first
+// unexpanded member of R and stopping when none is left expands exactly what
+// the two-heap loop expands.  The threshold is +inf until the set is full.
+#include "kernels.h"
+
+namespace ads {
+
+namespace {
+
+constexpr int HN_LANES = 8;        // lanes per neighbour: 8 x float4 = 32 coordinates a step
+constexpr int HN_GROUPS = ADS_WAVE / HN_LANES;
+constexpr int HN_SLOTS = 4;        // neighbours per lane group in flight
+constexpr int HN_UNROLL = 2;       // steps of 32 coordinates loaded at once
+
+__device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int wave_sum(int v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+struct Smem {
+    float *q;          // [D] rotated query
+    float *coef;       // [nb] test coefficients
+    uint64_t *rk;      // [nef] R (HNSW, HNSW+) or R2 (HNSW++), ascending
+    uint8_t *rx;       // [nef] expanded flags of rk
+    uint64_t *r1k;     // [K] R1 (HNSW++)
+    int *nbr;          // [HN_MAXDEG] neighbours being DCO'd
+    int *tb;           // [HN_MAXDEG] block where the DCO stopped at the expansion's threshold
+    float *psum;       // [HN_MAXDEG][nb] partial sums after each block
+};
+
+// Parallel DCOs of nbr[0..m) against r2 (squared threshold): every lane group
+// takes neighbours g, g + 8, g + 16, g + 24 together.  psum[j][b] receives the
+// sum after block b up to the block where the DCO stops (rejection or the last
+// block); tb[j] that block.
+__device__ void dco_phase(const HnswArgs &a, const Smem &sm, int m, float r2, int lane) {
+    const int gl = lane & (HN_LANES - 1);
+    const int g = lane / HN_LANES;
+    const int steps = a.D >> 5;
+    const int bps = 32 / a.dd;          // blocks per step
+    const int lpb = a.dd >> 2;          // lanes per block
+    const int nb = a.nb;
+    float S[HN_SLOTS];
+    int term[HN_SLOTS];
+    bool act[HN_SLOTS];
+    const float *row[HN_SLOTS];
+#pragma unroll
+    for (int t = 0; t < HN_SLOTS; ++t) {
+        int j = g + HN_GROUPS * t;
+        act[t] = j < m;
+        S[t] = 0.f;
+        term[t] = nb - 1;
+        row[t] = a.data + (act[t] ? (int64_t)sm.nbr[j] * a.D : 0) + gl * 4;
+    }
+    for (int s = 0; s < steps; s += HN_UNROLL) {
+        bool any = false;
+#pragma unroll
+        for (int t = 0; t < HN_SLOTS; ++t) any |= act[t];
+        if (!any) break;
+        float4 v[HN_SLOTS][HN_UNROLL];
+#pragma unroll
+        for (int t = 0; t < HN_SLOTS; ++t)
+#pragma unroll
+            for (int u = 0; u < HN_UNROLL; ++u)
+                if (act[t] && s + u < steps)
+                    v[t][u] = *reinterpret_cast<const float4 *>(row[t] + (s + u) * 32);
+#pragma unroll
+        for (int u = 0; u < HN_UNROLL; ++u) {
+            if (s + u >= steps) break;
+            const float4 qv = *reinterpret_cast<const float4 *>(sm.q + (s + u) * 32 + gl * 4);
+#pragma unroll
+            for (int t = 0; t < HN_SLOTS; ++t) {
+                if (!act[t]) continue;
+                const float y0 = v[t][u].x - qv.x, y1 = v[t][u].y - qv.y;
+                const float y2 = v[t][u].z - qv.z, y3 = v[t][u].w - qv.w;
+                float p = (y0 * y0 + y1 * y1) + (y2 * y2 + y3 * y3);
+                if (lpb >= 2) p += __shfl_xor(p, 1);
+                if (lpb >= 4) p += __shfl_xor(p, 2);
+                if (lpb >= 8) p += __shfl_xor(p, 4);
+                const int j = g + HN_GROUPS * t;
+                const int base = lane & ~(HN_LANES - 1);
+                for (int k = 0; k < bps; ++k) {
+                    const float bsum = __shfl(p, base + k * lpb);
+                    const int bi = (s + u) * bps + k;
+                    S[t] += bsum;
+                    if (gl == 0) sm.psum[j * nb + bi] = S[t];
+                    if (bi < nb - 1 && test_reject(S[t], sm.coef[bi], r2)) {
+                        term[t] = bi;
+                        act[t] = false;
+                        break;
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < HN_SLOTS; ++t) {
+        int j = g + HN_GROUPS * t;
+        if (j < m && gl == 0) sm.tb[j] = term[t];
+    }
+}
+
+// The sequential DCO of neighbour j at squared threshold r2 (<= the threshold
+// of its dco_phase), replayed from the stored sums.  Returns the block where
+// it stops; *pos / *s receive the positive flag and the sum there.
+__device__ int replay(const HnswArgs &a, const Smem &sm, int j, float r2, float r2_phase, bool *pos,
+                      float *s, int lane) {
+    const int nb = a.nb;
+    const int t0 = sm.tb[j];
+    int stop = t0;
+    if (r2 != r2_phase) {
+        const int lim = t0 < nb - 1 ? t0 : nb - 2;     // blocks that carry a test
+        stop = nb - 1;
+        for (int b0 = 0; b0 <= lim; b0 += ADS_WAVE) {
+            const int b = b0 + lane;
+            const bool rej = b <= lim && test_reject(sm.psum[j * nb + b], sm.coef[b], r2);
+            const uint64_t mask = wave_ballot(rej);
+            if (mask) {
+                stop = b0 + __ffsll((long long)mask) - 1;
+                break;
+            }
+        }
+    }
+    *s = sm.psum[j * nb + stop];
+    *pos = stop == nb - 1 && *s <= r2;
+    return stop;
+}
+
+// Inserts key into the ascending array k[0..n) of capacity cap (the caller has
+// checked that it belongs there); the largest key falls off a full array.
+// Returns the position.
+__device__ int sorted_insert(uint64_t *k, uint8_t *x, int &n, int cap, uint64_t key, int lane) {
+    int c = 0;
+    for (int i = lane; i < n; i += ADS_WAVE) c += k[i] < key;
+    const int p = wave_sum(c);
+    const int last = n < cap ? n : cap - 1;          // entries p..last-1 move up by one
+    for (int hi = last; hi > p; hi -= ADS_WAVE) {
+        const int lo = hi - ADS_WAVE > p ? hi - ADS_WAVE : p;
+        const int i = lo + lane;
+        uint64_t tk = 0;
+        uint8_t tx = 0;
+        if (i < hi) {
+            tk = k[i];
+            if (x) tx = x[i];
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (i < hi) {
+            k[i + 1] = tk;
+            if (x) x[i + 1] = tx;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (lane == 0) {
+        k[p] = key;
+        if (x) x[p] = 0;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (n < cap) ++n;
+    return p;
+}
+
+__device__ __forceinline__ void lds_sync() { __syncthreads(); }
+
+}  // namespace
+
+__global__ __launch_bounds__(ADS_WAVE) void hnsw_search_kernel(HnswArgs a) {
+    extern __shared__ __align__(16) unsigned char hn_smem[];
+    const int lane = threadIdx.x;
+    const int qi = blockIdx.x;
+    const int D = a.D, nb = a.nb;
+    Smem sm;
+    {
+        unsigned char *p = hn_smem;
+        sm.q = reinterpret_cast<float *>(p); p += (size_t)D * 4;
+        sm.psum = reinterpret_cast<float *>(p); p += (size_t)HN_MAXDEG * nb * 4;
+        sm.coef = reinterpret_cast<float *>(p); p += ((size_t)nb * 4 + 7) & ~(size_t)7;
+        sm.rk = reinterpret_cast<uint64_t *>(p); p += (size_t)a.nef * 8;
+        sm.r1k = reinterpret_cast<uint64_t *>(p); p += (size_t)a.K * 8;
+        sm.nbr = reinterpret_cast<int *>(p); p += HN_MAXDEG * 4;
+        sm.tb = reinterpret_cast<int *>(p); p += HN_MAXDEG * 4;
+        sm.rx = p;
+    }
+    const float *qg = a.qrot + (int64_t)qi * D;
+    for (int i = lane; i < D; i += ADS_WAVE) sm.q[i] = qg[i];
+    for (int i = lane; i < nb; i += ADS_WAVE) sm.coef[i] = a.coef[i];
+    lds_sync();
+
+    int64_t dcos = 0, dims = 0, hops = 0;
+    const int dd = a.dd;
+
+    // entry vertex: a DCO with threshold +inf
+    int cur = a.entry;
+    if (lane == 0) sm.nbr[0] = cur;
+    lds_sync();
+    dco_phase(a, sm, 1, __builtin_inff(), lane);
+    lds_sync();
+    float dcur = sm.psum[nb - 1];
+    dcos += 1;
+    dims += D;
+
+    // upper layers: greedy descent with the current distance as threshold
+    for (int l = a.max_level; l >= 1; --l) {
+        for (;;) {
+            const int32_t *rowp = a.up_adj + (a.up_off[cur] + (l - 1)) * (int64_t)a.M;
+            int v = lane < a.M ? rowp[lane] : -1;
+            const uint64_t valid = wave_ballot(v >= 0);
+            const int m = __popcll(valid);          // rows are -1 padded at the end
+            if (lane < m) sm.nbr[lane] = v;
+            lds_sync();
+            const float r0 = dcur;
+            dco_phase(a, sm, m, r0, lane);
+            lds_sync();
+            bool changed = false;
+            for (int j = 0; j < m; ++j) {
+                bool pos;
+                float s;
+                const int stop = replay(a, sm, j, dcur, r0, &pos, &s, lane);
+                dcos += 1;
+                dims += (int64_t)(stop + 1) * dd;
+                const int u = sm.nbr[j];
+                if (pos && make_key(s, (uint32_t)u) < make_key(dcur, (uint32_t)cur)) {
+                    cur = u;
+                    dcur = s;
+                    changed = true;
+                }
+            }
+            lds_sync();
+            if (!changed) break;
+        }
+    }
+
+    // layer 0: beam search
+    uint32_t *vis = a.visited + (int64_t)qi * a.vis_words;
+    if (lane == 0) atomicOr(vis + (cur >> 5), 1u << (cur & 31));
+    int nr = 0, nr1 = 0;
+    const bool pp = a.variant == ADS_HNSW_PP;
+    sorted_insert(sm.rk, sm.rx, nr, a.nef, make_key(dcur, (uint32_t)cur), lane);
+    if (pp) sorted_insert(sm.r1k, nullptr, nr1, a.K, make_key(dcur, (uint32_t)cur), lane);
+    lds_sync();
+    int cursor = 0;
+    for (;;) {
+        // pop: the first member of R not expanded yet
+        int p = -1;
+        for (int b0 = cursor; b0 < nr; b0 += ADS_WAVE) {
+            const int i = b0 + lane;
+            const uint64_t mask = wave_ballot(i < nr && !sm.rx[i]);
+            if (mask) {
+                p = b0 + __ffsll((long long)mask) - 1;
+                break;
+            }
+        }
+        if (p < 0) break;
+        lds_sync();
+        if (lane == 0) sm.rx[p] = 1;
+        cursor = p + 1;
+        hops += 1;
+        const int u = key_id(sm.rk[p]);
+        // neighbours not visited yet, in stored order
+        const int32_t *rowp = a.adj0 + (int64_t)u * a.M0;
+        int v = lane < a.M0 ? rowp[lane] : -1;
+        bool fresh = false;
+        if (v >= 0) {
+            const uint32_t bit = 1u << (v & 31);
+            fresh = (atomicOr(vis + (v >> 5), bit) & bit) == 0;
+        }
+        const uint64_t fm = wave_ballot(fresh);
+        const int m = __popcll(fm);
+        if (fresh) sm.nbr[__popcll(fm & ((1ull << lane) - 1))] = v;
+        lds_sync();
+        if (m == 0) continue;
+        auto threshold = [&]() -> float {
+            if (pp) return nr1 < a.K ? __builtin_inff() : key_dist2(sm.r1k[nr1 - 1]);
+            return nr < a.nef ? __builtin_inff() : key_dist2(sm.rk[nr - 1]);
+        };
+        const float r0 = threshold();
+        dco_phase(a, sm, m, r0, lane);
+        lds_sync();
+        for (int j = 0; j < m; ++j) {
+            bool pos;
+            float s;
+            const float r2 = threshold();
+            const int stop = replay(a, sm, j, r2, r0, &pos, &s, lane);
+            const int d = (stop + 1) * dd;
+            dcos += 1;
+            dims += d;
+            const uint32_t w = (uint32_t)sm.nbr[j];
+            if (!pp) {
+                if (!pos) continue;
+                const uint64_t key = make_key(s, w);
+                if (nr < a.nef || key < sm.rk[nr - 1]) {
+                    const int at = sorted_insert(sm.rk, sm.rx, nr, a.nef, key, lane);
+                    if (at < cursor) cursor = at;
+                }
+            } else {
+                if (pos) {
+                    const uint64_t key = make_key(s, w);
+                    if (nr1 < a.K || key < sm.r1k[nr1 - 1]) sorted_insert(sm.r1k, nullptr, nr1, a.K, key, lane);
+                }
+                const float obs = d == D ? s : (float)((double)s * (double)D / (double)d);
+                const uint64_t key2 = make_key(obs, w);
+                if (nr < a.nef || key2 < sm.rk[nr - 1]) {
+                    const int at = sorted_insert(sm.rk, sm.rx, nr, a.nef, key2, lane);
+                    if (at < cursor) cursor = at;
+                }
+            }
+            lds_sync();
+        }
+    }
+
+    // answer: the K nearest of R (HNSW, HNSW+) or R1 (HNSW++)
+    const uint64_t *res = pp ? sm.r1k : sm.rk;
+    const int nres = pp ? nr1 : nr;
+    for (int k = lane; k < a.K; k += ADS_WAVE) {
+        const int64_t o = (int64_t)qi * a.K + k;
+        if (k < nres) {
+            a.ids[o] = key_id(res[k]);
+            a.dist[o] = __builtin_sqrtf(key_dist2(res[k]));
+        } else {
+            a.ids[o] = -1;
+            a.dist[o] = __builtin_inff();
+        }
+    }
+    if (lane == 0) {
+        if (a.qstats) {
+            a.qstats[3 * (int64_t)qi + 0] = dcos;
+            a.qstats[3 * (int64_t)qi + 1] = dims;
+            a.qstats[3 * (int64_t)qi + 2] = hops;
+        }
+        if (a.stats) {
+            atomicAdd(a.stats + 0, (unsigned long long)dcos);
+            atomicAdd(a.stats + 1, (unsigned long long)dims);
+            atomicAdd(a.stats + 2, (unsigned long long)hops);
+        }
+    }
+}
+
+__global__ void hnsw_setup_kernel(float *coef, int nb, int dd, int D, double eps0, int method,
+                                  uint32_t *visited, int64_t words) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid < nb) coef[tid] = tid == nb - 1 ? 1.0f : test_coef((int)(tid + 1) * dd, D, eps0, method);
+    for (int64_t i = tid; i < words; i += (int64_t)gridDim.x * blockDim.x) visited[i] = 0u;
+}
+
+size_t hnsw_smem_bytes(int D, int nb, int nef, int K) {
+    size_t b = (size_t)D * 4 + (size_t)HN_MAXDEG * nb * 4 + (((size_t)nb * 4 + 7) & ~(size_t)7) +
+               (size_t)nef * 8 + (size_t)K * 8 + 2 * HN_MAXDEG * 4 + (size_t)nef;
+    return (b + 15) & ~(size_t)15;
+}
+
+hipError_t launch_hnsw_setup(float *coef, int nb, int dd, int D, double eps0, int method,
+                             uint32_t *visited, int64_t words, hipStream_t s) {
+    int64_t g = (words + ADS_WG - 1) / ADS_WG;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(hnsw_setup_kernel, dim3((unsigned)g), dim3(ADS_WG), 0, s, coef, nb, dd, D, eps0,
+                       method, visited, words);
+    return hipGetLastError();
+}
+
+hipError_t launch_hnsw_search(const HnswArgs &a, int nq, hipStream_t s) {
+    if (nq <= 0) return hipSuccess;
+    const size_t smem = hnsw_smem_bytes(a.D, a.nb, a.nef, a.K);
+    hipLaunchKernelGGL(hnsw_search_kernel, dim3((unsigned)nq), dim3(ADS_WAVE), smem, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace ads

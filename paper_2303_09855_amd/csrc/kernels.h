@@ -70,4 +70,27 @@ hipError_t launch_farthest(const int32_t *assign, const float *d2, int64_t n, in
 hipError_t launch_update_centres(const float *x, int64_t n, int D, const int32_t *assign, int nlist, float *cent,
                                  hipStream_t s);
 
+// Graph search (hnsw.hip)
+constexpr int HN_MAXDEG = 32;       // largest neighbour row (M0 on layer 0, M above)
+constexpr int HN_MAXBLOCKS = 128;   // largest D / delta_d
+struct HnswArgs {
+    const float *data;       // [n][D] transformed vectors, row-major
+    const int32_t *adj0;     // [n][M0] layer-0 neighbours, -1 padded
+    const int64_t *up_off;   // [n] first upper row of each vertex (-1 on layer 0 only)
+    const int32_t *up_adj;   // [rows][M] upper-layer neighbours, -1 padded
+    const float *qrot;       // [nq][D] transformed queries
+    const float *coef;       // [nb] test coefficients (1 for the last block)
+    uint32_t *visited;       // [nq][vis_words] bitmaps, zeroed before the launch
+    int64_t vis_words;
+    int64_t *ids;            // [nq][K]
+    float *dist;             // [nq][K]
+    int64_t *qstats;         // [nq][3] DCOs, sampled dims, expansions (or NULL)
+    unsigned long long *stats;  // [3] accumulators (or NULL)
+    int D, nb, dd, M0, M, entry, max_level, K, nef, variant;
+};
+size_t hnsw_smem_bytes(int D, int nb, int nef, int K);
+hipError_t launch_hnsw_setup(float *coef, int nb, int dd, int D, double eps0, int method,
+                             uint32_t *visited, int64_t words, hipStream_t s);
+hipError_t launch_hnsw_search(const HnswArgs &a, int nq, hipStream_t s);
+
 }  // namespace ads

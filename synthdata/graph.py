@@ -148,13 +148,21 @@ def _layer(x: np.ndarray, nodes: np.ndarray, m: int) -> dict:
     adj = np.full((len(nodes), m), -1, dtype=np.int64)
     adj[:, :m - 1] = final
     _join_components(x, nodes, adj, pos)
-    return {int(nodes[i]): adj[i] for i in range(len(nodes))}
+    out = {}
+    for i in range(len(nodes)):
+        row = adj[i][adj[i] >= 0]                 # ids first, -1 padding at the end
+        full = np.full(m, -1, dtype=np.int64)
+        full[:len(row)] = row
+        out[int(nodes[i])] = full
+    return out
 
 
 def _join_components(x: np.ndarray, nodes: np.ndarray, adj: np.ndarray, pos: dict) -> None:
     """Links every vertex into the part reachable from the first one: while a
     vertex is unreached, the lowest unreached one u is joined both ways to the
-    nearest reached vertex w that has a free slot (u's own last slot is free)."""
+    nearest reached vertex w that has a free slot (u's own last slot is free).
+    Stops early when no reached vertex has a free slot left (possible only for
+    tiny M)."""
     m = adj.shape[1]
     reached = np.zeros(len(nodes), dtype=bool)
     xs = x[nodes].astype(np.float64)
@@ -182,7 +190,7 @@ def _join_components(x: np.ndarray, nodes: np.ndarray, adj: np.ndarray, pos: dic
         d = np.sum((xs[cand] - xs[u]) ** 2, axis=1)
         w = int(cand[np.lexsort((cand, d))[0]])
         adj[w, m - 1] = nodes[u]
-        if adj[u, m - 1] < 0:
+        if adj[u, m - 1] < 0 and nodes[w] not in adj[u]:
             adj[u, m - 1] = nodes[w]
         flood(u)
 

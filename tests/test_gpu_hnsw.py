@@ -1,0 +1,197 @@
+"""GPU parity of the graph search (HNSW, HNSW+, HNSW++; Sections 2.2.1, 4, 5.1)
+against the FP64 oracle on the same seeded graph and vectors, through the C ABI.
+
+* Hand-traced searches (tests/golden/hnsw_tiny.json, full-distance variant):
+  ids, distances, DCOs, sampled dims and expansions exactly as traced.
+* Integer coordinates with the identity rotation: every distance and partial
+  sum is an exact integer in float32, so the GPU must reproduce the oracle's
+  search bit for bit (ids, distances, DCOs, dims, expansions) on every query
+  whose decisions the oracle does not flag as lying within 1e-6 of a test
+  boundary (Algorithm 1's boundaries are irrational, and HNSW++'s observed
+  distances sqrt(D/d) ||y|[1..d]|| can meet an exact one); at least 80% of
+  queries must be unflagged.
+* Float data with a random rotation: the paths may part at rounding-level
+  near-ties, so recall@K within 0.01 of the oracle's, DCO and dims totals
+  within 3%, every returned distance within 1e-5 of the FP64 distance of the
+  returned id.
+* Edge cases: no queries, K above the vertices reachable, a one-entry beam,
+  HNSW++ with N_ef below K.
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synthdata as sd
+from synthdata.graph import hnsw_graph
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def ads():
+    import paper_2303_09855_amd as m
+    m.load()
+    assert torch.cuda.is_available(), "the GPU tests need a visible GPU"
+    return m
+
+
+def _run(ads, ix, q, K, nef, eps0, variant):
+    qs = torch.zeros((q.shape[0], 3), dtype=torch.int64, device="cuda")
+    ids, dist = ads.hnsw_search(ix, q, K, nef, eps0=eps0, variant=variant, qstats=qs)
+    torch.cuda.synchronize()
+    return ids.cpu().numpy(), dist.cpu().numpy().astype(np.float64), qs.cpu().numpy()
+
+
+class _G:
+    pass
+
+
+def test_hand_traced_searches(ads):
+    """The ten-vertex graph of the golden file, its points embedded in D = 32
+    (the other coordinates zero for every vector and the query), full-distance
+    DCOs: every traced quantity reproduced (dims scale with D)."""
+    lines = [json.loads(l) for l in open(os.path.join(GOLDEN, "hnsw_tiny.json"))]
+    g0 = lines[1]
+    n = len(g0["points"])
+    g = _G()
+    g.levels = np.array(g0["levels"], np.int32)
+    g.adj0 = np.array(g0["adj0"], np.int32)
+    g.up_off = np.full(n, -1, np.int64)
+    rows = []
+    for v, nb in g0["up"].items():
+        g.up_off[int(v)] = len(rows)
+        rows.append(nb)
+    g.up_adj = np.array(rows, np.int32)
+    g.entry = g0["entry"]
+    D = 32
+    x = np.zeros((n, D), np.float32)
+    x[:, :2] = np.array(g0["points"], np.float32)
+    ix = ads.hnsw_create(x, None, g, delta_d=8)
+    try:
+        for c in lines[2:]:
+            if c["variant"] != oracle.HNSW_PLAIN:
+                continue
+            q = np.zeros((1, D), np.float32)
+            q[0, :2] = c.get("query", g0["query"])
+            ids, dist, qs = _run(ads, ix, q, c["K"], c["nef"], math.inf, ads.HNSW_PLAIN)
+            assert ids[0].tolist() == c["ids"], c["name"]
+            assert np.allclose(dist[0] ** 2, c["sq_dist"], rtol=1e-6), c["name"]
+            assert qs[0].tolist() == [c["dcos"], c["dims"] // 2 * D, c["hops"]], c["name"]
+    finally:
+        ix.free()
+
+
+@pytest.fixture(scope="module")
+def integer_graph(ads):
+    x = sd.mixture(4000, 128, 71, 1000)
+    q = sd.mixture(200, 128, 72, 1000)
+    g = hnsw_graph(x, M=8, seed=73)
+    return x, q, g
+
+
+@pytest.mark.parametrize("variant,eps0,dd,K,nef", [
+    (1, math.inf, 32, 10, 40),
+    (0, 2.1, 32, 10, 40),
+    (2, 2.1, 32, 10, 40),
+    (0, 1.0, 16, 10, 80),
+    (2, 1.0, 16, 10, 80),
+    (2, 2.1, 8, 20, 10),
+    (0, 2.1, 8, 1, 1),
+])
+def test_integer_data_is_bit_exact(ads, integer_graph, variant, eps0, dd, K, nef):
+    x, q, g = integer_graph
+    eye = np.eye(x.shape[1], dtype=np.float32)
+    ix = ads.hnsw_create(x, eye, g, delta_d=dd)
+    try:
+        ids, dist, qs = _run(ads, ix, q, K, nef, eps0, variant)
+    finally:
+        ix.free()
+    o_ids, o_dist, o_st = oracle.hnsw_search(x.astype(np.float64), q.astype(np.float64), g, K, nef,
+                                             eps0, dd, variant, rel=1e-6, rel_exact=0.0)
+    clean = o_st[:, 3] == 0
+    assert clean.mean() >= 0.8, clean.mean()
+    assert np.array_equal(ids[clean], o_ids[clean])
+    fin = np.isfinite(o_dist[clean])
+    assert np.allclose(dist[clean][fin] ** 2, o_dist[clean][fin] ** 2, rtol=1e-6, atol=0)
+    assert np.array_equal(qs[clean], o_st[clean, :3])
+
+
+@pytest.fixture(scope="module")
+def float_graph(ads):
+    x = sd.lowrank(8000, 256, 81, 82, latent=32, noise=0.05)
+    q = sd.lowrank(200, 256, 83, 82, latent=32, noise=0.05)
+    g = hnsw_graph(x, M=16, seed=84)
+    G = sd.gaussian_matrix(256, 85)
+    P32, _ = ads.make_rotation(G)
+    P64 = oracle.make_rotation(G)
+    return x, q, g, P32, P64
+
+
+@pytest.mark.parametrize("variant,eps0,nef", [(1, math.inf, 64), (0, 2.1, 64), (2, 2.1, 64),
+                                              (2, 2.1, 200)])
+def test_rotated_float_data_matches_oracle(ads, float_graph, variant, eps0, nef):
+    x, q, g, P32, P64 = float_graph
+    K = 10
+    ix = ads.hnsw_create(x, P32, g, delta_d=16)
+    try:
+        ids, dist, qs = _run(ads, ix, q, K, nef, eps0, variant)
+    finally:
+        ix.free()
+    xr, qr = oracle.rotate(x, P64), oracle.rotate(q, P64)
+    o_ids, o_dist, o_st = oracle.hnsw_search(xr, qr, g, K, nef, eps0, 16, variant)
+    _, gt = oracle.brute_knn(x, q, K)
+    ex = np.stack([oracle.exact_dist(x[np.maximum(ids[i], 0)], q[i]) for i in range(len(q))])
+    ex[ids < 0] = np.inf
+    o_ex = np.stack([oracle.exact_dist(x[o_ids[i]], q[i]) for i in range(len(q))])
+    r_gpu = oracle.recall(ids, ex, gt, K)
+    r_orc = oracle.recall(o_ids, o_ex, gt, K)
+    assert abs(r_gpu - r_orc) <= 0.01, (r_gpu, r_orc)
+    ok = ids >= 0
+    assert np.all(np.abs(dist[ok] - ex[ok]) <= 1e-5 * ex[ok] + 1e-6)
+    for col in (0, 1):
+        assert abs(qs[:, col].sum() / o_st[:, col].sum() - 1) <= 0.03, col
+    assert (ids == o_ids).all(axis=1).mean() >= 0.8
+
+
+def test_edge_cases(ads):
+    x = sd.mixture(40, 32, 91, 1000)
+    g = hnsw_graph(x, M=2, seed=92)
+    eye = np.eye(32, dtype=np.float32)
+    ix = ads.hnsw_create(x, eye, g, delta_d=8)
+    try:
+        q = sd.mixture(5, 32, 93, 1000)
+        ids, dist = ads.hnsw_search(ix, q[:0], 10, 10)
+        assert ids.shape == (0, 10)
+        # K = nef = 64 > n: every reachable vertex is returned, the rest padded
+        ids, dist, _ = _run(ads, ix, q, 64, 64, 2.1, ads.HNSW_PLUS)
+        o_ids, o_dist, _ = oracle.hnsw_search(x.astype(np.float64), q.astype(np.float64), g, 64, 64,
+                                              2.1, 8, 0, rel=1e-6)
+        assert np.array_equal(ids, o_ids)
+        assert np.all(ids[:, 40:] == -1) and np.all(np.isinf(dist[:, 40:]))
+        # HNSW++ with a beam narrower than the answer
+        ids, dist, qs = _run(ads, ix, q, 12, 4, 2.1, ads.HNSW_PP)
+        o_ids, o_dist, o_st = oracle.hnsw_search(x.astype(np.float64), q.astype(np.float64), g, 12, 4,
+                                                 2.1, 8, 2, rel=1e-6)
+        clean = o_st[:, 3] == 0
+        assert np.array_equal(ids[clean], o_ids[clean]) and np.array_equal(qs[clean], o_st[clean, :3])
+        with pytest.raises(ads.AdsError):
+            ads.hnsw_search(ix, q, 20, 10, variant=ads.HNSW_PLUS)     # nef < K
+    finally:
+        ix.free()
+    # ADSampling needs a rotated index
+    ix = ads.hnsw_create(x, None, g, delta_d=8)
+    try:
+        with pytest.raises(ads.AdsError):
+            ads.hnsw_search(ix, q, 5, 10, eps0=2.1, variant=ads.HNSW_PLUS)
+        ads.hnsw_search(ix, q, 5, 10, eps0=2.1, variant=ads.HNSW_PLAIN)
+    finally:
+        ix.free()

@@ -90,3 +90,52 @@ def test_tuning_knobs_validate_and_round_trip(ads):
     finally:
         ads.set_tuning(**saved)
     assert ads.get_tuning() == saved
+
+
+def _graph_call(lib, levels, adj0, up_off, up_adj, M0, M, entry, D=64, delta_d=16, rows=None):
+    levels = np.ascontiguousarray(levels, dtype=np.int32)
+    adj0 = np.ascontiguousarray(adj0, dtype=np.int32)
+    up_off = np.ascontiguousarray(up_off, dtype=np.int64)
+    up_adj = np.ascontiguousarray(up_adj, dtype=np.int32)
+    out = ctypes.c_void_p()
+    fake_base = ctypes.c_void_p(4096)       # never dereferenced: validation fails first
+    return lib.ads_hnsw_create(fake_base, len(levels), D, None, levels.ctypes.data, adj0.ctypes.data, M0,
+                               up_off.ctypes.data, up_adj.ctypes.data,
+                               up_adj.shape[0] if rows is None else rows, M, entry, delta_d, None,
+                               ctypes.byref(out))
+
+
+def test_graph_index_validates_the_graph_on_the_host(ads):
+    """ads_hnsw_create checks every row before it allocates or copies anything:
+    ids in range, -1 padding only at the end of a row, no duplicates, upper
+    neighbours present on their layer, the entry on the top layer, shapes the
+    kernels support."""
+    lib = ads.load()
+    levels = [1, 0, 0, 1]
+    adj0 = [[1, 2, -1], [0, 3, -1], [3, 0, -1], [2, 1, -1]]
+    up_off = [0, -1, -1, 1]
+    up_adj = [[3, -1], [0, -1]]
+    bad = [
+        (dict(adj0=[[1, 2, -1], [0, 4, -1], [3, 0, -1], [2, 1, -1]]), "out of range"),
+        (dict(adj0=[[1, -1, 2], [0, 3, -1], [3, 0, -1], [2, 1, -1]]), "after -1 padding"),
+        (dict(adj0=[[1, 1, -1], [0, 3, -1], [3, 0, -1], [2, 1, -1]]), "duplicate"),
+        (dict(adj0=[[1, 2, -2], [0, 3, -1], [3, 0, -1], [2, 1, -1]]), "neighbour id"),
+        (dict(up_adj=[[1, -1], [0, -1]]), "not on that layer"),
+        (dict(up_off=[0, -1, -1, 5]), "upper rows"),
+        (dict(entry=1), "level"),
+        (dict(entry=9), "entry"),
+        (dict(D=48), "multiple of 32"),
+        (dict(delta_d=64), "delta_d"),
+        (dict(M0=40), "M0"),
+    ]
+    for change, msg in bad:
+        args = dict(levels=levels, adj0=adj0, up_off=up_off, up_adj=up_adj, M0=3, M=2, entry=0)
+        args.update(change)
+        if args["M0"] != 3:
+            args["adj0"] = np.full((4, args["M0"]), -1)
+        assert _graph_call(lib, **args) == -1, change
+        assert msg in ads.last_error(), (change, ads.last_error())
+    # search-side checks need no device either
+    assert lib.ads_hnsw_search(None, None, 1, 10, 10, 2.1, 0, None, None, None, None, None, None) == -1
+    assert lib.ads_hnsw_workspace_size(None, 4) == 0
+    assert lib.ads_hnsw_free(None) == 0

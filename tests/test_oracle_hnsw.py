@@ -213,3 +213,38 @@ def test_band_flags_are_rare_on_integer_data():
     for variant in (oracle.HNSW_PLAIN, oracle.HNSW_PLUS, oracle.HNSW_PP):
         _, _, st = oracle.hnsw_search(x, q, g, 10, 50, 2.1, 32, variant, rel=1e-6, rel_exact=0.0)
         assert st[:, 3].mean() <= 0.05, (variant, st[:, 3].mean())
+
+
+@pytest.mark.parametrize("model,n,D,M,seed", [("mix", 2000, 128, 8, 73), ("mix", 40, 32, 2, 92),
+                                              ("lowrank", 1500, 64, 16, 84)])
+def test_graph_input_format(model, n, D, M, seed):
+    """The seeded graph meets the format both searches read: ids in range,
+    -1 padding only at the end of a row, no duplicates, at most M (2M on layer
+    0) neighbours, upper neighbours present on their layer, the entry on the
+    top layer, and (for M >= 4, where the free slots suffice) every vertex
+    reachable from the first one on every layer."""
+    x = sd.mixture(n, D, seed, 1000) if model == "mix" else sd.lowrank(n, D, seed, seed + 1, latent=8)
+    g = hnsw_graph(x, M=M, seed=seed)
+    assert g.adj0.shape == (n, 2 * M) and g.up_adj.shape[1] == M
+    assert g.levels[g.entry] == g.max_level == g.levels.max()
+    assert g.entry == int(np.flatnonzero(g.levels == g.max_level)[0])
+    for v in range(n):
+        rows = [(0, g.adj0[v])] + [(l, g.up_adj[g.up_off[v] + l - 1]) for l in range(1, g.levels[v] + 1)]
+        for l, r in rows:
+            ids = r[r >= 0]
+            assert np.all(r[len(ids):] == -1), (v, l)
+            assert len(set(ids.tolist())) == len(ids) and v not in ids
+            assert ids.max(initial=-1) < n
+            assert all(g.levels[u] >= l for u in ids)
+    for l in range(g.max_level + 1 if M >= 4 else 0):
+        nodes = np.flatnonzero(g.levels >= l)
+        seen = {int(nodes[0])}
+        stack = [int(nodes[0])]
+        while stack:
+            u = stack.pop()
+            r = g.adj0[u] if l == 0 else g.up_adj[g.up_off[u] + l - 1]
+            for v in r[r >= 0]:
+                if int(v) not in seen:
+                    seen.add(int(v))
+                    stack.append(int(v))
+        assert seen == set(nodes.tolist()), l
