@@ -62,12 +62,13 @@ def parse():
     ap.add_argument("--no-fds", action="store_true")
     ap.add_argument("--no-pds", action="store_true",
                     help="skip the PDScanning leg (IVF** on an unrotated index)")
-    ap.add_argument("--mode", default="search", choices=["search", "serve", "verify", "batched"],
+    ap.add_argument("--mode", default="search", choices=["search", "serve", "verify", "batched", "hnsw"],
                     help="search: the throughput benchmark (default); serve: the continuous-"
                          "batching request loop at Poisson arrival rates; verify: the fixed-"
                          "threshold failure-rate / dims sweep over eps0 and the linear-scan "
                          "feasibility run; batched: one captured search per batch with "
-                         "per-query K in {10, 100} and nprobe uniform on [8, 128]")
+                         "per-query K in {10, 100} and nprobe uniform on [8, 128]; hnsw: graph "
+                         "search (HNSW, HNSW+, HNSW++) on the workload's vectors")
     ap.add_argument("--verify-queries", type=int, default=20, help="verify mode: queries")
     ap.add_argument("--verify-n", type=int, default=200_000,
                     help="verify mode: base vectors of the linear scans (the first n of the workload)")
@@ -79,6 +80,9 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device-to-device copy first (reference kernel "
                          "of known size for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
+    ap.add_argument("--hnsw-m", type=int, default=16, help="hnsw mode: M (2M on layer 0)")
+    ap.add_argument("--nef", type=int, default=None,
+                    help="hnsw mode: use this N_ef for every variant instead of searching")
     ap.add_argument("--tune", default="",
                     help="scan scheduling knobs, e.g. sweep_log2=4,dense_frac=0.25 (ads_tuning fields)")
     ap.add_argument("--nprobe", type=int, default=None,
@@ -214,6 +218,9 @@ def main() -> int:
     if args.mode == "verify":
         ix.free()
         return verify(args, w, x, q, G)
+    if args.mode == "hnsw":
+        ix.free()
+        return hnsw(args, w, x, q, G, gt)
 
     p_ads, r_ads = operating_point(args.eps0, "ADSampling")
     ids_ads = last_ids[args.eps0]
@@ -408,6 +415,115 @@ def batched(args, w, ix, q, x):
             "dims_ratio": round(float(stv[ads.STAT_DIMS]) / max(1.0, float(stv[ads.STAT_DCOS]) * w.D), 5)}
     print(json.dumps(line), flush=True)
     plan.free()
+    ix.free()
+    return 0
+
+
+NEF_GRID = [10, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024]
+
+
+def hnsw(args, w, x, q, G, gt):
+    """Graph search on the workload's vectors: an HNSW-structured graph
+    (M, 2M on layer 0) built once, then HNSW (full distances), HNSW+ and HNSW++
+    (Sections 2.2.1, 4, 5.1), each at the smallest N_ef of NEF_GRID whose
+    recall@K reaches the target; QPS, DCOs and sampled dims of each."""
+    import torch
+
+    import oracle
+    import paper_2303_09855_amd as ads
+    from synthdata.graph import hnsw_graph_torch
+    K = args.K
+    t0 = time.time()
+    g = hnsw_graph_torch(x, M=args.hnsw_m, seed=w.kmeans_seed, progress=log)
+    log(f"graph built in {time.time() - t0:.1f}s (levels 0..{g.max_level}, layer-0 degree "
+        f"{(g.adj0 >= 0).sum(1).mean():.1f})")
+    P32, _ = ads.make_rotation(G)
+    ix = ads.hnsw_create(x, P32, g, delta_d=args.delta_d)
+    qd = torch.as_tensor(q).cuda()
+    torch.cuda.synchronize()
+
+    def recall_of(nef, variant):
+        ids, _ = ads.hnsw_search(ix, qd, K, nef, eps0=args.eps0, variant=variant)
+        torch.cuda.synchronize()
+        ids = ids.cpu().numpy()
+        return oracle.recall(ids, exact_for(x, q, ids), gt, K), ids
+
+    def operating_point(variant, label):
+        grid = [args.nef] if args.nef else [v for v in NEF_GRID if v >= K] or [K]
+        best = None
+        for nef in grid:
+            r, ids = recall_of(nef, variant)
+            log(f"{label}: nef {nef:5d} recall@{K} {r:.4f}")
+            best = (nef, r, ids)
+            if r >= args.target_recall:
+                break
+        return best
+
+    def timed(nef, variant, label):
+        for _ in range(args.warmup):
+            ads.hnsw_search(ix, qd, K, nef, eps0=args.eps0, variant=variant)
+        st = torch.zeros(3, dtype=torch.int64, device="cuda")
+        ads.hnsw_search(ix, qd, K, nef, eps0=args.eps0, variant=variant, stats=st)
+        ws = torch.empty(ads.hnsw_workspace_size(ix, w.nq) + 256, dtype=torch.uint8, device="cuda")
+        off = (-ws.data_ptr()) % 256
+        wsv = ws[off:]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            ads.hnsw_search(ix, qd, K, nef, eps0=args.eps0, variant=variant, workspace=wsv)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / args.steps
+        stv = st.cpu().numpy()
+        log(f"{label}: nef {nef} {ms:.3f} ms/step, {w.nq / (ms / 1e3):.0f} QPS")
+        return ms, stv
+
+    rows = {}
+    for variant, label in ((ads.HNSW_PLAIN, "HNSW"), (ads.HNSW_PLUS, "HNSW+"), (ads.HNSW_PP, "HNSW++")):
+        nef, r, ids = operating_point(variant, label)
+        ms, stv = timed(nef, variant, label)
+        rows[label] = {"nef": nef, "recall": round(r, 4), "ms_per_step": round(ms, 4),
+                       "qps": round(w.nq / (ms / 1e3), 1), "dcos_per_query": round(stv[0] / w.nq, 1),
+                       "dims_ratio": round(float(stv[1]) / max(1.0, float(stv[0]) * w.D), 5),
+                       "expansions_per_query": round(stv[2] / w.nq, 1),
+                       "dcos_per_s": round(float(stv[0]) / (ms / 1e3), 1),
+                       "dco_bytes_per_s": round(float(stv[1]) * 4 / (ms / 1e3), 1)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        nef = rows["HNSW++"]["nef"]
+        P64 = oracle.make_rotation(G)
+        xr = oracle.rotate(x, P64)
+        nsamp = min(w.nq, 200)
+        qr = oracle.rotate(q[:nsamp], P64)
+        threads = min(16, os.cpu_count() or 1)
+        t = time.perf_counter()
+        o_ids, _, o_st = oracle.hnsw_search(xr, qr, g, K, nef, args.eps0, args.delta_d, oracle.HNSW_PP,
+                                            threads=threads)
+        el = time.perf_counter() - t
+        t = time.perf_counter()
+        oracle.hnsw_search(xr, qr[:20], g, K, nef, args.eps0, args.delta_d, oracle.HNSW_PP, threads=1)
+        el1 = time.perf_counter() - t
+        o_rec = oracle.recall(o_ids, exact_for(x, q[:nsamp], o_ids), gt[:nsamp], K)
+        cpu = {"value": round(nsamp / el, 2), "unit": "queries/s", "cores": threads, "kind": "oracle",
+               "sample": f"HNSW++ at nef {nef} on the first {nsamp} queries (FP64); one thread: "
+                         f"{round(20 / el1, 2)} queries/s on 20 queries",
+               "oracle_recall": round(o_rec, 4)}
+        del xr
+    pp, plain, plus = rows["HNSW++"], rows["HNSW"], rows["HNSW+"]
+    line = {"metric": "graph search QPS @ recall@10>=0.95: HNSW++ / HNSW+ vs HNSW, same GPU",
+            "value": pp["qps"], "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": pp["ms_per_step"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"{w.name} vectors: N={w.n}, D={w.D}, {w.nq} queries; HNSW-structured "
+                                   f"graph M={args.hnsw_m}; K={K}, delta_d={args.delta_d}, eps0={args.eps0}"},
+            "hnsw": plain, "hnsw_plus": plus, "hnsw_pp": pp,
+            "speedup_pp_vs_hnsw": round(plain["ms_per_step"] / pp["ms_per_step"], 3),
+            "speedup_plus_vs_hnsw": round(plain["ms_per_step"] / plus["ms_per_step"], 3),
+            "roofline": {"bound": "hbm", "achieved": round(pp["dco_bytes_per_s"] / 1e9, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(pp["dco_bytes_per_s"] / 1e9 / HBM_PEAK_GBS, 4),
+                         "traffic": None, "kernel": "hnsw_search_kernel",
+                         "note": "sampled coordinates x 4 B per second (the bytes the DCOs need)"},
+            "cpu_baseline": cpu}
+    print(json.dumps(line), flush=True)
     ix.free()
     return 0
 
