@@ -419,7 +419,7 @@ def batched(args, w, ix, q, x):
     return 0
 
 
-NEF_GRID = [10, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024]
+NEF_GRID = [10, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096]
 
 
 def hnsw(args, w, x, q, G, gt):

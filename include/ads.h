@@ -475,7 +475,9 @@ uint64_t ads_hnsw_workspace_size(const ads_hnsw *ix, int32_t nq);
  *
  *   q        device [nq][D] float32 raw queries (rotated inside).
  *   K, nef   answer size and beam width N_ef (K <= nef for HNSW and HNSW+;
- *            HNSW++ keeps R1 of K and R2 of nef); 1 <= K <= 256, nef <= 1024.
+ *            HNSW++ keeps R1 of K and R2 of nef); 1 <= K <= 256, nef <= 4096
+ *            (D, K and nef together must fit the 64 KiB of LDS a workgroup may
+ *            use: 4 D + 128 D / delta_d + 9 nef + 8 K bytes, roughly).
  *   eps0     Algorithm 1's parameter (>= 0; +inf never rejects); ignored by
  *            ADS_HNSW_PLAIN.
  *   ids      device [nq][K] int64 out, ascending (distance, id); -1 padded.

@@ -1272,7 +1272,7 @@ extern "C" ads_status ads_hnsw_search(const ads_hnsw *ix, const float *q, int32_
     if (nq < 0) return fail(ADS_EINVAL, "nq must be >= 0");
     if (variant < ADS_HNSW_PLUS || variant > ADS_HNSW_PP) return fail(ADS_EINVAL, "unknown variant %d", variant);
     if (K < 1 || K > 256) return fail(ADS_EINVAL, "K must be in [1, 256] (got %d)", K);
-    if (nef < 1 || nef > 1024) return fail(ADS_EINVAL, "nef must be in [1, 1024] (got %d)", nef);
+    if (nef < 1 || nef > 4096) return fail(ADS_EINVAL, "nef must be in [1, 4096] (got %d)", nef);
     if (variant != ADS_HNSW_PP && nef < K) return fail(ADS_EINVAL, "nef (%d) must be >= K (%d)", nef, K);
     if (!(eps0 >= 0.f)) return fail(ADS_EINVAL, "eps0 must be >= 0 (got %g)", (double)eps0);
     if (!ix->P && variant != ADS_HNSW_PLAIN && !std::isinf(eps0))

@@ -31,14 +31,9 @@ namespace {
 constexpr int HN_LANES = 8;        // lanes per neighbour: 8 x float4 = 32 coordinates a step
 constexpr int HN_GROUPS = ADS_WAVE / HN_LANES;
 constexpr int HN_SLOTS = 4;        // neighbours per lane group in flight
-constexpr int HN_UNROLL = 2;       // steps of 32 coordinates loaded at once
+constexpr int HN_UNROLL = 4;       // steps of 32 coordinates loaded at once
 
 __device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
-
-__device__ __forceinline__ int wave_sum(int v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
 
 struct Smem {
     float *q;          // [D] rotated query
@@ -148,27 +143,48 @@ __device__ int replay(const HnswArgs &a, const Smem &sm, int j, float r2, float 
     return stop;
 }
 
-// Inserts key into the ascending array k[0..n) of capacity cap (the caller has
-// checked that it belongs there); the largest key falls off a full array.
-// Returns the position.
+// Inserts key into the ascending array k[0..n) of capacity cap (<= 4096; the
+// caller has checked that it belongs there); the largest key falls off a full
+// array.  Returns the position.  The position comes from two ballots (every
+// ceil(n/64)-th key, then the keys of the bracketing stretch); the move is done
+// from the top down in stretches of 256 entries, four per lane, each stretch
+// read completely before it is written one place higher.
 __device__ int sorted_insert(uint64_t *k, uint8_t *x, int &n, int cap, uint64_t key, int lane) {
-    int c = 0;
-    for (int i = lane; i < n; i += ADS_WAVE) c += k[i] < key;
-    const int p = wave_sum(c);
+    int p = 0;
+    if (n > 0) {
+        const int S = (n + ADS_WAVE - 1) / ADS_WAVE;
+        const int i1 = lane * S;
+        const int b = __popcll(wave_ballot(i1 < n && k[i1] < key));
+        if (b > 0) {
+            const int base = (b - 1) * S + 1;
+            const int i2 = base + lane;
+            const bool lt = lane < S - 1 && i2 < n && k[i2] < key;
+            p = base + __popcll(wave_ballot(lt));
+        }
+    }
     const int last = n < cap ? n : cap - 1;          // entries p..last-1 move up by one
-    for (int hi = last; hi > p; hi -= ADS_WAVE) {
-        const int lo = hi - ADS_WAVE > p ? hi - ADS_WAVE : p;
-        const int i = lo + lane;
-        uint64_t tk = 0;
-        uint8_t tx = 0;
-        if (i < hi) {
-            tk = k[i];
-            if (x) tx = x[i];
+    for (int hi = last; hi > p; hi -= 4 * ADS_WAVE) {
+        const int lo = hi - 4 * ADS_WAVE > p ? hi - 4 * ADS_WAVE : p;
+        uint64_t tk[4];
+        uint8_t tx[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = lo + lane + c * ADS_WAVE;
+            tk[c] = 0;
+            tx[c] = 0;
+            if (i < hi) {
+                tk[c] = k[i];
+                if (x) tx[c] = x[i];
+            }
         }
         __builtin_amdgcn_wave_barrier();
-        if (i < hi) {
-            k[i + 1] = tk;
-            if (x) x[i + 1] = tx;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = lo + lane + c * ADS_WAVE;
+            if (i < hi) {
+                k[i + 1] = tk[c];
+                if (x) x[i + 1] = tx[c];
+            }
         }
         __builtin_amdgcn_wave_barrier();
     }

@@ -106,6 +106,8 @@ def integer_graph(ads):
     (2, 1.0, 16, 10, 80),
     (2, 2.1, 8, 20, 10),
     (0, 2.1, 8, 1, 1),
+    (0, 2.1, 16, 10, 2000),
+    (2, 2.1, 16, 100, 120),
 ])
 def test_integer_data_is_bit_exact(ads, integer_graph, variant, eps0, dd, K, nef):
     x, q, g = integer_graph
