@@ -43,6 +43,8 @@ struct Smem {
     uint64_t *r1k;     // [K] R1 (HNSW++)
     int *nbr;          // [HN_MAXDEG] neighbours being DCO'd
     int *tb;           // [HN_MAXDEG] block where the DCO stopped at the expansion's threshold
+    float *cm;         // [HN_MAXDEG] max over tested blocks of S_b / coef_b (DCOs that reached d = D)
+    float *rcoef;      // [nb] 1 / coef (0 where no test)
     float *psum;       // [HN_MAXDEG][nb] partial sums after each block
 };
 
@@ -57,7 +59,7 @@ __device__ void dco_phase(const HnswArgs &a, const Smem &sm, int m, float r2, in
     const int bps = 32 / a.dd;          // blocks per step
     const int lpb = a.dd >> 2;          // lanes per block
     const int nb = a.nb;
-    float S[HN_SLOTS];
+    float S[HN_SLOTS], cmx[HN_SLOTS];
     int term[HN_SLOTS];
     bool act[HN_SLOTS];
     const float *row[HN_SLOTS];
@@ -66,6 +68,7 @@ __device__ void dco_phase(const HnswArgs &a, const Smem &sm, int m, float r2, in
         int j = g + HN_GROUPS * t;
         act[t] = j < m;
         S[t] = 0.f;
+        cmx[t] = 0.f;
         term[t] = nb - 1;
         row[t] = a.data + (act[t] ? (int64_t)sm.nbr[j] * a.D : 0) + gl * 4;
     }
@@ -101,10 +104,13 @@ __device__ void dco_phase(const HnswArgs &a, const Smem &sm, int m, float r2, in
                     const int bi = (s + u) * bps + k;
                     S[t] += bsum;
                     if (gl == 0) sm.psum[j * nb + bi] = S[t];
-                    if (bi < nb - 1 && test_reject(S[t], sm.coef[bi], r2)) {
-                        term[t] = bi;
-                        act[t] = false;
-                        break;
+                    if (bi < nb - 1) {
+                        if (test_reject(S[t], sm.coef[bi], r2)) {
+                            term[t] = bi;
+                            act[t] = false;
+                            break;
+                        }
+                        cmx[t] = fmaxf(cmx[t], S[t] * sm.rcoef[bi]);
                     }
                 }
             }
@@ -113,8 +119,20 @@ __device__ void dco_phase(const HnswArgs &a, const Smem &sm, int m, float r2, in
 #pragma unroll
     for (int t = 0; t < HN_SLOTS; ++t) {
         int j = g + HN_GROUPS * t;
-        if (j < m && gl == 0) sm.tb[j] = term[t];
+        if (j < m && gl == 0) {
+            sm.tb[j] = term[t];
+            sm.cm[j] = cmx[t];
+        }
     }
+}
+
+// A DCO that reached d = D at its phase's threshold rejects at no block for a
+// threshold r2 above max_b S_b / coef_b: then coef_b r2 exceeds every S_b by
+// far more than the rounding of the product and of the stored quotient (a
+// margin of 1e-5), so test_reject is false at every block without evaluating
+// them.  Closer thresholds are decided block by block.
+__device__ __forceinline__ bool no_test_below(const Smem &sm, int j, int t0, int nb, float r2) {
+    return t0 == nb - 1 && r2 > sm.cm[j] * 1.00001f;
 }
 
 // The sequential DCO of neighbour j at squared threshold r2 (<= the threshold
@@ -125,7 +143,7 @@ __device__ int replay(const HnswArgs &a, const Smem &sm, int j, float r2, float 
     const int nb = a.nb;
     const int t0 = sm.tb[j];
     int stop = t0;
-    if (r2 != r2_phase) {
+    if (r2 != r2_phase && !no_test_below(sm, j, t0, nb, r2)) {
         const int lim = t0 < nb - 1 ? t0 : nb - 2;     // blocks that carry a test
         stop = nb - 1;
         for (int b0 = 0; b0 <= lim; b0 += ADS_WAVE) {
@@ -197,7 +215,37 @@ __device__ int sorted_insert(uint64_t *k, uint8_t *x, int &n, int cap, uint64_t 
     return p;
 }
 
-__device__ __forceinline__ void lds_sync() { __syncthreads(); }
+// The workgroup is one wave: ordering its LDS accesses needs no s_barrier.
+__device__ __forceinline__ void lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// replay() evaluated by one lane for its own neighbour j.
+__device__ __forceinline__ int outcome_lane(const HnswArgs &a, const Smem &sm, int j, float r2, float r2_phase,
+                                            bool *pos, float *s) {
+    const int nb = a.nb;
+    const int t0 = sm.tb[j];
+    int stop = t0;
+    if (r2 != r2_phase && !no_test_below(sm, j, t0, nb, r2)) {
+        const int lim = t0 < nb - 1 ? t0 : nb - 2;     // blocks that carry a test
+        stop = nb - 1;
+        for (int b = 0; b <= lim; ++b)
+            if (test_reject(sm.psum[j * nb + b], sm.coef[b], r2)) {
+                stop = b;
+                break;
+            }
+    }
+    *s = sm.psum[j * nb + stop];
+    *pos = stop == nb - 1 && *s <= r2;
+    return stop;
+}
 
 }  // namespace
 
@@ -216,11 +264,17 @@ __global__ __launch_bounds__(ADS_WAVE) void hnsw_search_kernel(HnswArgs a) {
         sm.r1k = reinterpret_cast<uint64_t *>(p); p += (size_t)a.K * 8;
         sm.nbr = reinterpret_cast<int *>(p); p += HN_MAXDEG * 4;
         sm.tb = reinterpret_cast<int *>(p); p += HN_MAXDEG * 4;
+        sm.cm = reinterpret_cast<float *>(p); p += HN_MAXDEG * 4;
+        sm.rcoef = reinterpret_cast<float *>(p); p += ((size_t)nb * 4 + 7) & ~(size_t)7;
         sm.rx = p;
     }
     const float *qg = a.qrot + (int64_t)qi * D;
     for (int i = lane; i < D; i += ADS_WAVE) sm.q[i] = qg[i];
-    for (int i = lane; i < nb; i += ADS_WAVE) sm.coef[i] = a.coef[i];
+    for (int i = lane; i < nb; i += ADS_WAVE) {
+        const float c = a.coef[i];
+        sm.coef[i] = c;
+        sm.rcoef[i] = __builtin_isinf(c) ? 0.f : 1.0f / c;
+    }
     lds_sync();
 
     int64_t dcos = 0, dims = 0, hops = 0;
@@ -313,35 +367,61 @@ __global__ __launch_bounds__(ADS_WAVE) void hnsw_search_kernel(HnswArgs a) {
         const float r0 = threshold();
         dco_phase(a, sm, m, r0, lane);
         lds_sync();
-        for (int j = 0; j < m; ++j) {
-            bool pos;
-            float s;
+        // Replay of the sequential loop: all remaining neighbours are
+        // evaluated at the current threshold at once (lane = neighbour); the
+        // first one whose outcome changes a set ("hot") is then applied, the
+        // threshold re-read, and the evaluation repeats after it.  Neighbours
+        // before the hot one change nothing, so their outcomes at this
+        // threshold are the sequential ones.
+        int j = 0;
+        while (j < m) {
             const float r2 = threshold();
-            const int stop = replay(a, sm, j, r2, r0, &pos, &s, lane);
-            const int d = (stop + 1) * dd;
+            const bool full = nr >= a.nef, full1 = nr1 >= a.K;
+            const uint64_t rmax = full ? sm.rk[nr - 1] : KEY_NONE;
+            const uint64_t r1max = pp && full1 ? sm.r1k[nr1 - 1] : KEY_NONE;
+            int stop = 0;
+            bool pos = false, hot = false;
+            float sv = 0.f;
+            if (lane >= j && lane < m) {
+                stop = outcome_lane(a, sm, lane, r2, r0, &pos, &sv);
+                const uint32_t w = (uint32_t)sm.nbr[lane];
+                const int d = (stop + 1) * dd;
+                if (!pp) {
+                    hot = pos && make_key(sv, w) < rmax;
+                } else {
+                    const float obs = d == D ? sv : (float)((double)sv * (double)D / (double)d);
+                    hot = (pos && make_key(sv, w) < r1max) || make_key(obs, w) < rmax;
+                }
+            }
+            const uint64_t hm = wave_ballot(hot);
+            const int k = hm ? __ffsll((long long)hm) - 1 : m;
+            dims += wave_sum(lane >= j && lane < k ? (stop + 1) * dd : 0);
+            dcos += k - j;
+            if (k == m) break;
+            const int sk = __shfl(stop, k);
+            const float s = __shfl(sv, k);
+            const bool pk = __shfl(pos ? 1 : 0, k) != 0;
+            const int d = (sk + 1) * dd;
             dcos += 1;
             dims += d;
-            const uint32_t w = (uint32_t)sm.nbr[j];
+            const uint32_t w = (uint32_t)sm.nbr[k];
             if (!pp) {
-                if (!pos) continue;
-                const uint64_t key = make_key(s, w);
-                if (nr < a.nef || key < sm.rk[nr - 1]) {
-                    const int at = sorted_insert(sm.rk, sm.rx, nr, a.nef, key, lane);
-                    if (at < cursor) cursor = at;
-                }
+                const int at = sorted_insert(sm.rk, sm.rx, nr, a.nef, make_key(s, w), lane);
+                if (at < cursor) cursor = at;
             } else {
-                if (pos) {
+                if (pk) {
                     const uint64_t key = make_key(s, w);
-                    if (nr1 < a.K || key < sm.r1k[nr1 - 1]) sorted_insert(sm.r1k, nullptr, nr1, a.K, key, lane);
+                    if (key < r1max) sorted_insert(sm.r1k, nullptr, nr1, a.K, key, lane);
                 }
                 const float obs = d == D ? s : (float)((double)s * (double)D / (double)d);
                 const uint64_t key2 = make_key(obs, w);
-                if (nr < a.nef || key2 < sm.rk[nr - 1]) {
+                if (key2 < rmax) {
                     const int at = sorted_insert(sm.rk, sm.rx, nr, a.nef, key2, lane);
                     if (at < cursor) cursor = at;
                 }
             }
             lds_sync();
+            j = k + 1;
         }
     }
 
@@ -380,8 +460,8 @@ __global__ void hnsw_setup_kernel(float *coef, int nb, int dd, int D, double eps
 }
 
 size_t hnsw_smem_bytes(int D, int nb, int nef, int K) {
-    size_t b = (size_t)D * 4 + (size_t)HN_MAXDEG * nb * 4 + (((size_t)nb * 4 + 7) & ~(size_t)7) +
-               (size_t)nef * 8 + (size_t)K * 8 + 2 * HN_MAXDEG * 4 + (size_t)nef;
+    size_t b = (size_t)D * 4 + (size_t)HN_MAXDEG * nb * 4 + 2 * (((size_t)nb * 4 + 7) & ~(size_t)7) +
+               (size_t)nef * 8 + (size_t)K * 8 + 3 * HN_MAXDEG * 4 + (size_t)nef;
     return (b + 15) & ~(size_t)15;
 }
 
