@@ -106,7 +106,7 @@ struct SparseOut {
 template <int DT, int DD, class Sink>
 __device__ __forceinline__ SparseOut sparse_run(const SparseCtx &c, uint64_t *list0, uint64_t *list1, int n,
                                                 int bcur, Sink sink) {
-    unsigned long long my_dims = 0, my_pos = 0;
+    uint32_t my_dims = 0, my_pos = 0;      // per lane and call: at most 64 pairs x D
     constexpr int EB = Elem<DT>::bytes;
     const int lane = threadIdx.x & 63;
     const uint64_t lanemask_lt = (1ull << lane) - 1ull;
@@ -137,11 +137,17 @@ __device__ __forceinline__ SparseOut sparse_run(const SparseCtx &c, uint64_t *li
                 part = block_partial<DT, DD>(op, c.qrot + (int64_t)c.qidx[jj] * D + blk * DD, 0.f);
             }
             // S after each block, added in block order (the canonical order,
-            // independent of G): one lane of the group per round
-            float sb = gi == 0 ? s0 + part : 0.f;
-            for (int t = 1; t < G; ++t) {
-                const float prev = row_shr1(sb);
-                if (gi == t) sb = prev + part;
+            // independent of G): after step t the first t + 1 lanes of every
+            // group hold S_prev + p_0 + ... + p_gi, each lane adding its own
+            // partial to its left neighbour's sum; the group's first lane keeps
+            // s0 + p_0
+            const bool g0 = gi == 0;
+            float sb = g0 ? s0 + part : part;
+#pragma unroll
+            for (int t = 1; t < 16; ++t) {
+                if (t >= G) break;
+                const float y = row_shr1(sb) + part;
+                sb = g0 ? sb : y;
             }
             const int d = (blk + 1) * DD;
             const float r2 = pv ? c.r2s[jj] : 0.f;
@@ -156,7 +162,7 @@ __device__ __forceinline__ SparseOut sparse_run(const SparseCtx &c, uint64_t *li
             if (pv && gi == 0) {
                 if (grm) {
                     const int first = __ffsll((long long)grm) - 1;       // lane index of the event
-                    my_dims += (unsigned long long)(bcur + first - (lane & ~(G - 1)) + 1) * DD;
+                    my_dims += (uint32_t)(bcur + first - (lane & ~(G - 1)) + 1) * DD;
                 } else if (bcur + glast + 1 >= nb) {
                     my_dims += D;
                     if (slast <= r2) {

@@ -197,3 +197,47 @@ def test_edge_cases(ads):
         ads.hnsw_search(ix, q, 5, 10, eps0=2.1, variant=ads.HNSW_PLAIN)
     finally:
         ix.free()
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_full_size_d960_graph(ads):
+    """The graph benchmark's configuration: the 1M x 960 vectors and 1,000
+    queries of the D = 960 workload, the seeded HNSW-structured graph (M = 16,
+    built on the GPU with torch), K = 10, delta_d = 16, eps0 = 2.1, each
+    variant at its benchmark N_ef.  All queries on the GPU; 40 sampled queries
+    through the FP64 oracle on the same graph: recall on the sample within
+    0.03 of the oracle's, DCO and dims totals within 3%, at least 70% of the
+    sampled answers identical; every returned distance exact within 1e-5;
+    recall over all queries >= 0.95 (the operating point)."""
+    from synthdata.graph import hnsw_graph_torch
+    w = sd.WORKLOADS["ivf_d960"]
+    x = sd.base_vectors(w)
+    q = sd.query_vectors(w)
+    G = sd.rotation_gaussian(w)
+    g = hnsw_graph_torch(x, M=16, seed=w.kmeans_seed)
+    P32, _ = ads.make_rotation(G)
+    ix = ads.hnsw_create(x, P32, g, delta_d=16)
+    P64 = oracle.make_rotation(G)
+    sample = np.arange(0, w.nq, w.nq // 40)[:40]
+    xr = oracle.rotate(x, P64)
+    qr = oracle.rotate(q[sample], P64)
+    _, gt = oracle.brute_knn(x, q, 10)
+    try:
+        for variant, nef in ((ads.HNSW_PLAIN, 2048), (ads.HNSW_PLUS, 2048), (ads.HNSW_PP, 3072)):
+            ids, dist, qs = _run(ads, ix, q, 10, nef, 2.1, variant)
+            ex = np.stack([oracle.exact_dist(x[np.maximum(ids[i], 0)], q[i]) for i in range(w.nq)])
+            ok = ids >= 0
+            assert ok.all()
+            assert np.all(np.abs(dist - ex) <= 1e-5 * ex + 1e-6)
+            assert oracle.recall(ids, ex, gt, 10) >= 0.95, variant
+            o_ids, _, o_st = oracle.hnsw_search(xr, qr, g, 10, nef, 2.1, 16, variant)
+            o_ex = np.stack([oracle.exact_dist(x[o_ids[i]], q[s]) for i, s in enumerate(sample)])
+            r_gpu = oracle.recall(ids[sample], ex[sample], gt[sample], 10)
+            r_orc = oracle.recall(o_ids, o_ex, gt[sample], 10)
+            assert abs(r_gpu - r_orc) <= 0.03, (variant, r_gpu, r_orc)
+            for col in (0, 1):
+                assert abs(qs[sample, col].sum() / o_st[:, col].sum() - 1) <= 0.03, (variant, col)
+            assert (ids[sample] == o_ids).all(axis=1).mean() >= 0.7, variant
+    finally:
+        ix.free()
