@@ -107,7 +107,8 @@ hipError_t gemm_nt_f32(const float *A, int64_t lda, const float *B, int64_t ldb,
                        int64_t ldc, int64_t M, int64_t N, int K, hipStream_t s) {
     if (M <= 0 || N <= 0) return hipSuccess;
     const int64_t tiles128 = ((M + 127) / 128) * ((N + 127) / 128);
-    if (tiles128 < 256)
+    // 64x64 tiles until there are enough 128x128 tiles for four per CU
+    if (tiles128 < 1024)
         gemm_launch<32>(A, lda, B, ldb, C, ldc, M, N, K, s);
     else
         gemm_launch<64>(A, lda, B, ldb, C, ldc, M, N, K, s);
