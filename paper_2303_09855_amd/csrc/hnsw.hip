@@ -16,12 +16,13 @@
 // outcome, the sampled dimensions and the observed distance are exactly those
 // of the one-at-a-time loop over the same floating-point sums.
 //
-// Sets are sorted arrays of (squared distance, id) keys in LDS (lexicographic
-// order, so no two keys tie).  S is the set of R's (R2's) members not expanded
-// yet: with these keys an evicted member can never be expanded later, because
-// R's largest key only shrinks once R is full, so popping the first
-// unexpanded member of R and stopping when none is left expands exactly what
-// the two-heap loop expands.  The threshold is +inf until the set is full.
+// Sets hold (squared distance, id) keys in LDS (lexicographic order, so no two
+// keys tie).  S is the set of R's (R2's) members not expanded yet: with these
+// keys an evicted member can never be expanded later, because R's largest key
+// only shrinks once R is full, so popping the smallest unexpanded member of R
+// and stopping when none is left expands exactly what the two-heap loop
+// expands.  R is unsorted (pops and the largest key by reductions), R1 is a
+// sorted array.  The threshold is +inf until the set is full.
 #include "kernels.h"
 
 namespace ads {
@@ -216,6 +217,61 @@ __device__ int sorted_insert(uint64_t *k, uint8_t *x, int &n, int cap, uint64_t 
 }
 
 // The workgroup is one wave: ordering its LDS accesses needs no s_barrier.
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+    const uint32_t lo = __shfl_xor((uint32_t)v, m), hi = __shfl_xor((uint32_t)(v >> 32), m);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Smallest key among the entries of k[0..n) whose flag equals want, and its
+// index (-1 when there is none); every lane returns the same pair.  Keys are
+// distinct, so the minimum is unique.
+__device__ int argmin_flag(const uint64_t *k, const uint8_t *x, int n, uint8_t want, int lane, uint64_t *kout) {
+    uint64_t best = KEY_NONE;
+    int bi = -1;
+    for (int i = lane; i < n; i += ADS_WAVE) {
+        const uint64_t v = k[i];
+        if (x[i] == want && v < best) {
+            best = v;
+            bi = i;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t ob = shfl_xor_u64(best, o);
+        const int oi = __shfl_xor(bi, o);
+        if (ob < best) {
+            best = ob;
+            bi = oi;
+        }
+    }
+    *kout = best;
+    return bi;
+}
+
+// Largest key of k[0..n) (n >= 1) and its index, the same on every lane.
+__device__ int argmax_all(const uint64_t *k, int n, int lane, uint64_t *kout) {
+    uint64_t best = 0;
+    int bi = -1;
+    for (int i = lane; i < n; i += ADS_WAVE) {
+        const uint64_t v = k[i];
+        if (bi < 0 || v > best) {
+            best = v;
+            bi = i;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t ob = shfl_xor_u64(best, o);
+        const int oi = __shfl_xor(bi, o);
+        if (oi >= 0 && (bi < 0 || ob > best)) {
+            best = ob;
+            bi = oi;
+        }
+    }
+    *kout = best;
+    return bi;
+}
+
 __device__ __forceinline__ void lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -324,29 +380,36 @@ __global__ __launch_bounds__(ADS_WAVE) void hnsw_search_kernel(HnswArgs a) {
     // layer 0: beam search
     uint32_t *vis = a.visited + (int64_t)qi * a.vis_words;
     if (lane == 0) atomicOr(vis + (cur >> 5), 1u << (cur & 31));
+    // R (R2 for HNSW++) is kept unsorted: a pop takes the smallest key not yet
+    // expanded, and a full set keeps its largest key (the threshold and the
+    // entry an insertion replaces) in rmaxk / rmaxi; both come from one pass
+    // over the set and a wave reduction.  R1 (K entries) stays sorted.
     int nr = 0, nr1 = 0;
+    uint64_t rmaxk = KEY_NONE;
+    int rmaxi = -1;
     const bool pp = a.variant == ADS_HNSW_PP;
-    sorted_insert(sm.rk, sm.rx, nr, a.nef, make_key(dcur, (uint32_t)cur), lane);
+    auto r_insert = [&](uint64_t key) {
+        const int at = nr < a.nef ? nr : rmaxi;
+        if (lane == 0) {
+            sm.rk[at] = key;
+            sm.rx[at] = 0;
+        }
+        lds_sync();
+        if (nr < a.nef) ++nr;
+        if (nr == a.nef) rmaxi = argmax_all(sm.rk, nr, lane, &rmaxk);
+    };
+    r_insert(make_key(dcur, (uint32_t)cur));
     if (pp) sorted_insert(sm.r1k, nullptr, nr1, a.K, make_key(dcur, (uint32_t)cur), lane);
     lds_sync();
-    int cursor = 0;
     for (;;) {
-        // pop: the first member of R not expanded yet
-        int p = -1;
-        for (int b0 = cursor; b0 < nr; b0 += ADS_WAVE) {
-            const int i = b0 + lane;
-            const uint64_t mask = wave_ballot(i < nr && !sm.rx[i]);
-            if (mask) {
-                p = b0 + __ffsll((long long)mask) - 1;
-                break;
-            }
-        }
+        // pop: the nearest member of R not expanded yet
+        uint64_t pkey;
+        const int p = argmin_flag(sm.rk, sm.rx, nr, 0, lane, &pkey);
         if (p < 0) break;
         lds_sync();
         if (lane == 0) sm.rx[p] = 1;
-        cursor = p + 1;
         hops += 1;
-        const int u = key_id(sm.rk[p]);
+        const int u = key_id(pkey);
         // neighbours not visited yet, in stored order
         const int32_t *rowp = a.adj0 + (int64_t)u * a.M0;
         int v = lane < a.M0 ? rowp[lane] : -1;
@@ -362,7 +425,7 @@ __global__ __launch_bounds__(ADS_WAVE) void hnsw_search_kernel(HnswArgs a) {
         if (m == 0) continue;
         auto threshold = [&]() -> float {
             if (pp) return nr1 < a.K ? __builtin_inff() : key_dist2(sm.r1k[nr1 - 1]);
-            return nr < a.nef ? __builtin_inff() : key_dist2(sm.rk[nr - 1]);
+            return nr < a.nef ? __builtin_inff() : key_dist2(rmaxk);
         };
         const float r0 = threshold();
         dco_phase(a, sm, m, r0, lane);
@@ -377,7 +440,7 @@ __global__ __launch_bounds__(ADS_WAVE) void hnsw_search_kernel(HnswArgs a) {
         while (j < m) {
             const float r2 = threshold();
             const bool full = nr >= a.nef, full1 = nr1 >= a.K;
-            const uint64_t rmax = full ? sm.rk[nr - 1] : KEY_NONE;
+            const uint64_t rmax = full ? rmaxk : KEY_NONE;
             const uint64_t r1max = pp && full1 ? sm.r1k[nr1 - 1] : KEY_NONE;
             int stop = 0;
             bool pos = false, hot = false;
@@ -406,8 +469,7 @@ __global__ __launch_bounds__(ADS_WAVE) void hnsw_search_kernel(HnswArgs a) {
             dims += d;
             const uint32_t w = (uint32_t)sm.nbr[k];
             if (!pp) {
-                const int at = sorted_insert(sm.rk, sm.rx, nr, a.nef, make_key(s, w), lane);
-                if (at < cursor) cursor = at;
+                r_insert(make_key(s, w));
             } else {
                 if (pk) {
                     const uint64_t key = make_key(s, w);
@@ -415,27 +477,33 @@ __global__ __launch_bounds__(ADS_WAVE) void hnsw_search_kernel(HnswArgs a) {
                 }
                 const float obs = d == D ? s : (float)((double)s * (double)D / (double)d);
                 const uint64_t key2 = make_key(obs, w);
-                if (key2 < rmax) {
-                    const int at = sorted_insert(sm.rk, sm.rx, nr, a.nef, key2, lane);
-                    if (at < cursor) cursor = at;
-                }
+                if (key2 < rmax) r_insert(key2);
             }
             lds_sync();
             j = k + 1;
         }
     }
 
-    // answer: the K nearest of R (HNSW, HNSW+) or R1 (HNSW++)
-    const uint64_t *res = pp ? sm.r1k : sm.rk;
-    const int nres = pp ? nr1 : nr;
-    for (int k = lane; k < a.K; k += ADS_WAVE) {
-        const int64_t o = (int64_t)qi * a.K + k;
-        if (k < nres) {
-            a.ids[o] = key_id(res[k]);
-            a.dist[o] = __builtin_sqrtf(key_dist2(res[k]));
+    // answer: the K nearest of R (HNSW, HNSW+; every member is expanded now,
+    // flag 1, and is taken out in ascending order) or R1 (HNSW++, sorted)
+    for (int k = 0; k < a.K; ++k) {
+        uint64_t key = KEY_NONE;
+        if (pp) {
+            if (k < nr1) key = sm.r1k[k];
         } else {
-            a.ids[o] = -1;
-            a.dist[o] = __builtin_inff();
+            const int i = argmin_flag(sm.rk, sm.rx, nr, 1, lane, &key);
+            if (i >= 0 && lane == 0) sm.rx[i] = 2;
+            lds_sync();
+        }
+        if (lane == 0) {
+            const int64_t o = (int64_t)qi * a.K + k;
+            if (key != KEY_NONE) {
+                a.ids[o] = key_id(key);
+                a.dist[o] = __builtin_sqrtf(key_dist2(key));
+            } else {
+                a.ids[o] = -1;
+                a.dist[o] = __builtin_inff();
+            }
         }
     }
     if (lane == 0) {
