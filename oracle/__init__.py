@@ -62,7 +62,7 @@ METHOD_ADS, METHOD_FDS, METHOD_PDS = 0, 1, 2
 def build() -> str:
     """Compile the C part with gcc (always recompiles)."""
     os.makedirs(_BUILD, exist_ok=True)
-    tmp = _SO + ".tmp"
+    tmp = f"{_SO}.{os.getpid()}.tmp"     # concurrent builds never share a file
     cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall", "-o", tmp, *SOURCES,
            "-lm", "-lpthread"]
     subprocess.run(cmd, check=True)

@@ -28,9 +28,7 @@
 // compacted into an LDS list and finish in the pair-list phase
 // (scan_sparse.h).  The tile's positives are folded into each query's local
 // KNN set and lower its threshold before the next tile.
-//
-// This is the register-dense variant; scan_mfma.hip evaluates the dense phase
-// on the matrix cores and takes the same decisions.
+
 #pragma once
 #include "scan_sparse.h"
 
