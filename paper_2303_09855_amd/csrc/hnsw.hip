@@ -228,12 +228,23 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
 __device__ int argmin_flag(const uint64_t *k, const uint8_t *x, int n, uint8_t want, int lane, uint64_t *kout) {
     uint64_t best = KEY_NONE;
     int bi = -1;
-    for (int i = lane; i < n; i += ADS_WAVE) {
-        const uint64_t v = k[i];
-        if (x[i] == want && v < best) {
-            best = v;
-            bi = i;
+    // four entries per lane are read before any is compared
+    for (int i0 = lane; i0 < n; i0 += 4 * ADS_WAVE) {
+        uint64_t v[4];
+        bool ok[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = i0 + c * ADS_WAVE;
+            ok[c] = i < n;
+            v[c] = ok[c] ? k[i] : KEY_NONE;
+            ok[c] = ok[c] && x[i] == want;
         }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (ok[c] && v[c] < best) {
+                best = v[c];
+                bi = i0 + c * ADS_WAVE;
+            }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -252,12 +263,19 @@ __device__ int argmin_flag(const uint64_t *k, const uint8_t *x, int n, uint8_t w
 __device__ int argmax_all(const uint64_t *k, int n, int lane, uint64_t *kout) {
     uint64_t best = 0;
     int bi = -1;
-    for (int i = lane; i < n; i += ADS_WAVE) {
-        const uint64_t v = k[i];
-        if (bi < 0 || v > best) {
-            best = v;
-            bi = i;
+    for (int i0 = lane; i0 < n; i0 += 4 * ADS_WAVE) {
+        uint64_t v[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = i0 + c * ADS_WAVE;
+            v[c] = i < n ? k[i] : 0;
         }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (i0 + c * ADS_WAVE < n && (bi < 0 || v[c] > best)) {
+                best = v[c];
+                bi = i0 + c * ADS_WAVE;
+            }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -292,11 +310,24 @@ __device__ __forceinline__ int outcome_lane(const HnswArgs &a, const Smem &sm, i
     if (r2 != r2_phase && !no_test_below(sm, j, t0, nb, r2)) {
         const int lim = t0 < nb - 1 ? t0 : nb - 2;     // blocks that carry a test
         stop = nb - 1;
-        for (int b = 0; b <= lim; ++b)
-            if (test_reject(sm.psum[j * nb + b], sm.coef[b], r2)) {
-                stop = b;
+        // four blocks are read before any is tested
+        for (int b0 = 0; b0 <= lim; b0 += 4) {
+            float ps[4], cf[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int b = b0 + c <= lim ? b0 + c : lim;
+                ps[c] = sm.psum[j * nb + b];
+                cf[c] = sm.coef[b];
+            }
+            int hit = -1;
+#pragma unroll
+            for (int c = 3; c >= 0; --c)
+                if (b0 + c <= lim && test_reject(ps[c], cf[c], r2)) hit = b0 + c;
+            if (hit >= 0) {
+                stop = hit;
                 break;
             }
+        }
     }
     *s = sm.psum[j * nb + stop];
     *pos = stop == nb - 1 && *s <= r2;
