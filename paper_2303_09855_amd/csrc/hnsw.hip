@@ -49,16 +49,35 @@ struct Smem {
     float *psum;       // [HN_MAXDEG][nb] partial sums after each block
 };
 
+// Exchanges inside a group of 8 lanes (DPP, no LDS round trip): the value of
+// lane gl ^ 1, gl ^ 2 (quad permutations) and gl ^ 4 (a row shift by four
+// lanes in either direction; both neighbours of an 8-lane group lie in the
+// same 16-lane row).
+__device__ __forceinline__ float dpp_xor1(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float dpp_xor2(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float dpp_xor4(float x, bool upper) {
+    const int up = __builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x114, 0xf, 0xf, false);   // lane - 4
+    const int dn = __builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x104, 0xf, 0xf, false);   // lane + 4
+    return __int_as_float(upper ? up : dn);
+}
+
 // Parallel DCOs of nbr[0..m) against r2 (squared threshold): every lane group
 // takes neighbours g, g + 8, g + 16, g + 24 together.  psum[j][b] receives the
 // sum after block b up to the block where the DCO stops (rejection or the last
-// block); tb[j] that block.
-__device__ void dco_phase(const HnswArgs &a, const Smem &sm, int m, float r2, int lane) {
+// block); tb[j] that block.  A lane holds 4 coordinates of a step of 32; the
+// block sums are reduced over the block's lanes (a fixed pairwise tree, the
+// same value in every lane of the group) and added to S in block order.
+template <int DD>
+__device__ __forceinline__ void dco_phase(const HnswArgs &a, const Smem &sm, int m, float r2, int lane) {
+    constexpr int BPS = 32 / DD;        // blocks per step
     const int gl = lane & (HN_LANES - 1);
     const int g = lane / HN_LANES;
+    const bool upper = (gl & 4) != 0;
     const int steps = a.D >> 5;
-    const int bps = 32 / a.dd;          // blocks per step
-    const int lpb = a.dd >> 2;          // lanes per block
     const int nb = a.nb;
     float S[HN_SLOTS], cmx[HN_SLOTS];
     int term[HN_SLOTS];
@@ -79,39 +98,71 @@ __device__ void dco_phase(const HnswArgs &a, const Smem &sm, int m, float r2, in
         for (int t = 0; t < HN_SLOTS; ++t) any |= act[t];
         if (!any) break;
         float4 v[HN_SLOTS][HN_UNROLL];
+        // every load is issued, from a valid address (the row's first step
+        // where the slot is idle or past the end), so that they all go out
+        // together before the first is used
 #pragma unroll
         for (int t = 0; t < HN_SLOTS; ++t)
 #pragma unroll
-            for (int u = 0; u < HN_UNROLL; ++u)
-                if (act[t] && s + u < steps)
-                    v[t][u] = *reinterpret_cast<const float4 *>(row[t] + (s + u) * 32);
+            for (int u = 0; u < HN_UNROLL; ++u) {
+                const int su = act[t] && s + u < steps ? s + u : 0;
+                v[t][u] = *reinterpret_cast<const float4 *>(row[t] + su * 32);
+            }
 #pragma unroll
         for (int u = 0; u < HN_UNROLL; ++u) {
             if (s + u >= steps) break;
             const float4 qv = *reinterpret_cast<const float4 *>(sm.q + (s + u) * 32 + gl * 4);
+            // the step's test coefficients, shared by the slots
+            float cf[BPS], rc[BPS];
+#pragma unroll
+            for (int k = 0; k < BPS; ++k) {
+                cf[k] = sm.coef[(s + u) * BPS + k];
+                rc[k] = sm.rcoef[(s + u) * BPS + k];
+            }
 #pragma unroll
             for (int t = 0; t < HN_SLOTS; ++t) {
                 if (!act[t]) continue;
                 const float y0 = v[t][u].x - qv.x, y1 = v[t][u].y - qv.y;
                 const float y2 = v[t][u].z - qv.z, y3 = v[t][u].w - qv.w;
                 float p = (y0 * y0 + y1 * y1) + (y2 * y2 + y3 * y3);
-                if (lpb >= 2) p += __shfl_xor(p, 1);
-                if (lpb >= 4) p += __shfl_xor(p, 2);
-                if (lpb >= 8) p += __shfl_xor(p, 4);
+                // bsum[k]: the sum over the lanes of block k
+                float bsum[BPS];
+                if constexpr (DD == 8) {
+                    p += dpp_xor1(p);                 // pairs: block gl >> 1
+                    const float o2 = dpp_xor2(p);
+                    // the even and odd block of this lane's quad, then of the other quad
+                    const bool odd = (gl & 2) != 0;
+                    const float lo = odd ? o2 : p, hi = odd ? p : o2;
+                    const float lo4 = dpp_xor4(lo, upper), hi4 = dpp_xor4(hi, upper);
+                    bsum[0] = upper ? lo4 : lo;
+                    bsum[1] = upper ? hi4 : hi;
+                    bsum[BPS > 2 ? 2 : 0] = upper ? lo : lo4;
+                    bsum[BPS > 3 ? 3 : 0] = upper ? hi : hi4;
+                } else if constexpr (DD == 16) {
+                    p += dpp_xor1(p);
+                    p += dpp_xor2(p);                 // quads: block gl >> 2
+                    const float o = dpp_xor4(p, upper);
+                    bsum[0] = upper ? o : p;
+                    bsum[BPS - 1] = upper ? p : o;
+                } else {
+                    p += dpp_xor1(p);
+                    p += dpp_xor2(p);
+                    p += dpp_xor4(p, upper);
+                    bsum[0] = p;
+                }
                 const int j = g + HN_GROUPS * t;
-                const int base = lane & ~(HN_LANES - 1);
-                for (int k = 0; k < bps; ++k) {
-                    const float bsum = __shfl(p, base + k * lpb);
-                    const int bi = (s + u) * bps + k;
-                    S[t] += bsum;
+#pragma unroll
+                for (int k = 0; k < BPS; ++k) {
+                    const int bi = (s + u) * BPS + k;
+                    S[t] += bsum[k];
                     if (gl == 0) sm.psum[j * nb + bi] = S[t];
                     if (bi < nb - 1) {
-                        if (test_reject(S[t], sm.coef[bi], r2)) {
+                        if (test_reject(S[t], cf[k], r2)) {
                             term[t] = bi;
                             act[t] = false;
                             break;
                         }
-                        cmx[t] = fmaxf(cmx[t], S[t] * sm.rcoef[bi]);
+                        cmx[t] = fmaxf(cmx[t], S[t] * rc[k]);
                     }
                 }
             }
@@ -216,10 +267,49 @@ __device__ int sorted_insert(uint64_t *k, uint8_t *x, int &n, int cap, uint64_t 
     return p;
 }
 
-// The workgroup is one wave: ordering its LDS accesses needs no s_barrier.
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
-    const uint32_t lo = __shfl_xor((uint32_t)v, m), hi = __shfl_xor((uint32_t)(v >> 32), m);
-    return ((uint64_t)hi << 32) | lo;
+// Wave-wide reductions without LDS round trips: DPP exchanges inside each
+// 16-lane row (lane ^ 1, lane ^ 2, then rotations by 4 and 8, after which every
+// lane of a row holds the row's result), then the four rows' results read
+// with readlane and combined; every lane returns the same value.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, CTRL, 0xf, 0xf, false);
+}
+
+// (key, index) pairs: keeps the pair for which better(new, new index, old,
+// old index) holds.
+template <int CTRL, class Better>
+__device__ __forceinline__ void best_step(uint64_t &k, int &i, Better better) {
+    const uint32_t lo = dpp_u32<CTRL>((uint32_t)k), hi = dpp_u32<CTRL>((uint32_t)(k >> 32));
+    const int oi = (int)dpp_u32<CTRL>((uint32_t)i);
+    const uint64_t ok = ((uint64_t)hi << 32) | lo;
+    if (better(ok, oi, k, i)) {
+        k = ok;
+        i = oi;
+    }
+}
+
+template <class Better>
+__device__ __forceinline__ void wave_best(uint64_t &k, int &i, Better better) {
+    best_step<0xB1>(k, i, better);      // quad_perm 1,0,3,2
+    best_step<0x4E>(k, i, better);      // quad_perm 2,3,0,1
+    best_step<0x124>(k, i, better);     // row_ror:4
+    best_step<0x128>(k, i, better);     // row_ror:8
+    uint64_t bk = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(k >> 32), 0) << 32) |
+                  (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)k, 0);
+    int bi = __builtin_amdgcn_readlane(i, 0);
+#pragma unroll
+    for (int r = 16; r < ADS_WAVE; r += 16) {
+        const uint64_t rk = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(k >> 32), r) << 32) |
+                            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)k, r);
+        const int ri = __builtin_amdgcn_readlane(i, r);
+        if (better(rk, ri, bk, bi)) {
+            bk = rk;
+            bi = ri;
+        }
+    }
+    k = bk;
+    i = bi;
 }
 
 // Smallest key among the entries of k[0..n) whose flag equals want, and its
@@ -246,15 +336,7 @@ __device__ int argmin_flag(const uint64_t *k, const uint8_t *x, int n, uint8_t w
                 bi = i0 + c * ADS_WAVE;
             }
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const uint64_t ob = shfl_xor_u64(best, o);
-        const int oi = __shfl_xor(bi, o);
-        if (ob < best) {
-            best = ob;
-            bi = oi;
-        }
-    }
+    wave_best(best, bi, [](uint64_t ok, int, uint64_t k, int) { return ok < k; });
     *kout = best;
     return bi;
 }
@@ -277,15 +359,7 @@ __device__ int argmax_all(const uint64_t *k, int n, int lane, uint64_t *kout) {
                 bi = i0 + c * ADS_WAVE;
             }
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const uint64_t ob = shfl_xor_u64(best, o);
-        const int oi = __shfl_xor(bi, o);
-        if (oi >= 0 && (bi < 0 || ob > best)) {
-            best = ob;
-            bi = oi;
-        }
-    }
+    wave_best(best, bi, [](uint64_t ok, int oi, uint64_t k, int i) { return oi >= 0 && (i < 0 || ok > k); });
     *kout = best;
     return bi;
 }
@@ -296,9 +370,18 @@ __device__ __forceinline__ void lds_sync() {
 }
 
 __device__ __forceinline__ int wave_sum(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    v += (int)dpp_u32<0xB1>((uint32_t)v);
+    v += (int)dpp_u32<0x4E>((uint32_t)v);
+    v += (int)dpp_u32<0x124>((uint32_t)v);
+    v += (int)dpp_u32<0x128>((uint32_t)v);
+    return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) + __builtin_amdgcn_readlane(v, 32) +
+           __builtin_amdgcn_readlane(v, 48);
+}
+
+// x of lane k (k the same on every lane).
+__device__ __forceinline__ int lane_value(int x, int k) { return __builtin_amdgcn_readlane(x, k); }
+__device__ __forceinline__ float lane_value(float x, int k) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), k));
 }
 
 // replay() evaluated by one lane for its own neighbour j.
@@ -336,6 +419,7 @@ __device__ __forceinline__ int outcome_lane(const HnswArgs &a, const Smem &sm, i
 
 }  // namespace
 
+template <int DD>
 __global__ __launch_bounds__(ADS_WAVE) void hnsw_search_kernel(HnswArgs a) {
     extern __shared__ __align__(16) unsigned char hn_smem[];
     const int lane = threadIdx.x;
@@ -365,13 +449,13 @@ __global__ __launch_bounds__(ADS_WAVE) void hnsw_search_kernel(HnswArgs a) {
     lds_sync();
 
     int64_t dcos = 0, dims = 0, hops = 0;
-    const int dd = a.dd;
+    constexpr int dd = DD;
 
     // entry vertex: a DCO with threshold +inf
     int cur = a.entry;
     if (lane == 0) sm.nbr[0] = cur;
     lds_sync();
-    dco_phase(a, sm, 1, __builtin_inff(), lane);
+    dco_phase<DD>(a, sm, 1, __builtin_inff(), lane);
     lds_sync();
     float dcur = sm.psum[nb - 1];
     dcos += 1;
@@ -387,7 +471,7 @@ __global__ __launch_bounds__(ADS_WAVE) void hnsw_search_kernel(HnswArgs a) {
             if (lane < m) sm.nbr[lane] = v;
             lds_sync();
             const float r0 = dcur;
-            dco_phase(a, sm, m, r0, lane);
+            dco_phase<DD>(a, sm, m, r0, lane);
             lds_sync();
             bool changed = false;
             for (int j = 0; j < m; ++j) {
@@ -459,7 +543,7 @@ __global__ __launch_bounds__(ADS_WAVE) void hnsw_search_kernel(HnswArgs a) {
             return nr < a.nef ? __builtin_inff() : key_dist2(rmaxk);
         };
         const float r0 = threshold();
-        dco_phase(a, sm, m, r0, lane);
+        dco_phase<DD>(a, sm, m, r0, lane);
         lds_sync();
         // Replay of the sequential loop: all remaining neighbours are
         // evaluated at the current threshold at once (lane = neighbour); the
@@ -492,9 +576,9 @@ __global__ __launch_bounds__(ADS_WAVE) void hnsw_search_kernel(HnswArgs a) {
             dims += wave_sum(lane >= j && lane < k ? (stop + 1) * dd : 0);
             dcos += k - j;
             if (k == m) break;
-            const int sk = __shfl(stop, k);
-            const float s = __shfl(sv, k);
-            const bool pk = __shfl(pos ? 1 : 0, k) != 0;
+            const int sk = lane_value(stop, k);
+            const float s = lane_value(sv, k);
+            const bool pk = lane_value(pos ? 1 : 0, k) != 0;
             const int d = (sk + 1) * dd;
             dcos += 1;
             dims += d;
@@ -577,7 +661,12 @@ hipError_t launch_hnsw_setup(float *coef, int nb, int dd, int D, double eps0, in
 hipError_t launch_hnsw_search(const HnswArgs &a, int nq, hipStream_t s) {
     if (nq <= 0) return hipSuccess;
     const size_t smem = hnsw_smem_bytes(a.D, a.nb, a.nef, a.K);
-    hipLaunchKernelGGL(hnsw_search_kernel, dim3((unsigned)nq), dim3(ADS_WAVE), smem, s, a);
+    switch (a.dd) {
+        case 8: hipLaunchKernelGGL(hnsw_search_kernel<8>, dim3((unsigned)nq), dim3(ADS_WAVE), smem, s, a); break;
+        case 16: hipLaunchKernelGGL(hnsw_search_kernel<16>, dim3((unsigned)nq), dim3(ADS_WAVE), smem, s, a); break;
+        case 32: hipLaunchKernelGGL(hnsw_search_kernel<32>, dim3((unsigned)nq), dim3(ADS_WAVE), smem, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
