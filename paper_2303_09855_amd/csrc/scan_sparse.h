@@ -155,11 +155,12 @@ __device__ __forceinline__ SparseOut sparse_run(const SparseCtx &c, uint64_t *li
             const uint64_t rm = __ballot(ev);
             const uint64_t gmask = ((1ull << G) - 1ull) << (lane & ~(G - 1));
             const uint64_t grm = rm & gmask;
-            // the group's last block and the value of S there
+            // the group's last block and the value of S there; the lane that
+            // evaluated it decides for the group
             const int glast = min(G, nb - bcur) - 1;
-            const float slast = __shfl(sb, (lane & ~(G - 1)) + glast, 64);
+            const float slast = sb;
             bool keep = false;
-            if (pv && gi == 0) {
+            if (pv && gi == glast) {
                 if (grm) {
                     const int first = __ffsll((long long)grm) - 1;       // lane index of the event
                     my_dims += (uint32_t)(bcur + first - (lane & ~(G - 1)) + 1) * DD;
