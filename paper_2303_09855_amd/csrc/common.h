@@ -136,6 +136,22 @@ __device__ __forceinline__ void lds_bitonic_sort(uint64_t *buf, int n) {
 }
 
 // ---------------------------------------------------------------------------
+// Inclusive prefix sum over the 64 lanes of a wave (every lane active), by DPP:
+// shifts by 1, 2, 4 and 8 lanes inside each 16-lane row, then the last lane of
+// row 0 (row 2) added to row 1 (row 3) and lane 31 added to rows 2 and 3.  No
+// LDS round trip; integer sums, so the result is exact.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);   // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);   // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);   // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);   // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);   // row_bcast:31
+    return x;
+}
+
+// ---------------------------------------------------------------------------
 // Workgroup radix select: the k-th smallest (1-based) of n uint64 keys produced
 // by get(i), passes of 8 bits from the most significant byte; it stops early
 // once a single key carries the selected prefix.  The workgroup has 256
@@ -159,12 +175,7 @@ __device__ uint64_t radix_kth(Get get, int n, int k, uint32_t *hist, uint32_t *m
         // inclusive prefix over the bins (within each wave, then across waves);
         // the bin holding the kk-th key is the one whose range covers kk
         const uint32_t h = hist[t];
-        uint32_t x = h;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(x, o);
-            if (lane >= o) x += y;
-        }
+        const uint32_t x = wave_incl_scan(h);
         if (lane == 63) misc[4 + wv] = x;
         __syncthreads();
         uint32_t base = 0;
@@ -220,12 +231,7 @@ __device__ uint64_t group_kth(Get get, int n, int k, uint32_t *hist, uint32_t *m
             // lane t owns bins 4t .. 4t+3; the bin whose cumulative range covers kk wins
             const uint32_t h0 = hist[4 * t], h1 = hist[4 * t + 1], h2 = hist[4 * t + 2], h3 = hist[4 * t + 3];
             const uint32_t sum = h0 + h1 + h2 + h3;
-            uint32_t x = sum;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t y = __shfl_up(x, o);
-                if (t >= o) x += y;
-            }
+            const uint32_t x = wave_incl_scan(sum);
             const uint32_t c0 = x - sum, c1 = c0 + h0, c2 = c1 + h1, c3 = c2 + h2, c4 = c3 + h3;
             if (c0 < kk && kk <= c1) { misc[0] = 4 * t; misc[1] = kk - c0; misc[2] = h0; }
             if (c1 < kk && kk <= c2) { misc[0] = 4 * t + 1; misc[1] = kk - c1; misc[2] = h1; }
@@ -258,12 +264,7 @@ __device__ uint64_t group_kth(Get get, int n, int k, uint32_t *hist, uint32_t *m
 template <int W>
 __device__ int group_excl_scan(int v, int *wtot, int &total) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o);
-        if (lane >= o) x += y;
-    }
+    const int x = (int)wave_incl_scan((uint32_t)v);
     __syncthreads();
     if (lane == 63) wtot[w] = x;
     __syncthreads();

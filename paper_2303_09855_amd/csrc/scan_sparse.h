@@ -28,32 +28,6 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// An opaque copy of x: values derived from it are computed where they are
-// used instead of being hoisted out of loops and kept in registers.
-__device__ __forceinline__ int opaque(int x) {
-    asm volatile("" : "+v"(x));
-    return x;
-}
-
-__device__ __forceinline__ int wave_sum(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
-// Exclusive prefix sum over the wave's lanes; *total receives the sum.
-__device__ __forceinline__ int wave_excl_scan(int v, int &total) {
-    const int lane = threadIdx.x & 63;
-    int x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o);
-        if (lane >= o) x += y;
-    }
-    total = __shfl(x, 63);
-    return x - v;
-}
-
 // Canonical block partial: s + sum_k (o_k - q_k)^2 over DD coordinates, fused
 // multiply-adds in coordinate order.
 template <int DT, int DD>
