@@ -31,8 +31,9 @@ namespace {
 
 constexpr int HN_LANES = 8;        // lanes per neighbour: 8 x float4 = 32 coordinates a step
 constexpr int HN_GROUPS = ADS_WAVE / HN_LANES;
-constexpr int HN_SLOTS = 4;        // neighbours per lane group in flight
-constexpr int HN_UNROLL = 4;       // steps of 32 coordinates loaded at once
+constexpr int HN_WAVES = 4;        // waves per query: wave 0 searches, every wave DCOs 8 neighbours
+constexpr int HN_UNROLL = 8;       // steps of 32 coordinates loaded at once
+static_assert(HN_GROUPS * HN_WAVES == HN_MAXDEG, "one neighbour per lane group and wave");
 
 __device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
 
@@ -47,6 +48,7 @@ struct Smem {
     float *cm;         // [HN_MAXDEG] max over tested blocks of S_b / coef_b (DCOs that reached d = D)
     float *rcoef;      // [nb] 1 / coef (0 where no test)
     float *psum;       // [HN_MAXDEG][nb] partial sums after each block
+    int *job;          // [3] the DCO phase wave 0 hands to the other waves: m, r2 bits, stop flag
 };
 
 // Exchanges inside a group of 8 lanes (DPP, no LDS round trip): the value of
@@ -65,116 +67,96 @@ __device__ __forceinline__ float dpp_xor4(float x, bool upper) {
     return __int_as_float(upper ? up : dn);
 }
 
-// Parallel DCOs of nbr[0..m) against r2 (squared threshold): every lane group
-// takes neighbours g, g + 8, g + 16, g + 24 together.  psum[j][b] receives the
-// sum after block b up to the block where the DCO stops (rejection or the last
-// block); tb[j] that block.  A lane holds 4 coordinates of a step of 32; the
-// block sums are reduced over the block's lanes (a fixed pairwise tree, the
-// same value in every lane of the group) and added to S in block order.
+// Parallel DCOs of nbr[0..m) against r2 (squared threshold): wave `slot`
+// takes neighbours 8 slot .. 8 slot + 7, one per group of 8 lanes.
+// psum[j][b] receives the sum after block b up to the block where the DCO
+// stops (rejection or the last block); tb[j] that block.  A lane holds 4
+// coordinates of a step of 32; the block sums are reduced over the block's
+// lanes (a fixed pairwise tree, the same value in every lane of the group) and
+// added to S in block order.
 template <int DD>
-__device__ __forceinline__ void dco_phase(const HnswArgs &a, const Smem &sm, int m, float r2, int lane) {
+__device__ __forceinline__ void dco_phase(const HnswArgs &a, const Smem &sm, int m, float r2, int lane, int slot) {
     constexpr int BPS = 32 / DD;        // blocks per step
     const int gl = lane & (HN_LANES - 1);
-    const int g = lane / HN_LANES;
+    const int j = lane / HN_LANES + HN_GROUPS * slot;
     const bool upper = (gl & 4) != 0;
     const int steps = a.D >> 5;
     const int nb = a.nb;
-    float S[HN_SLOTS], cmx[HN_SLOTS];
-    int term[HN_SLOTS];
-    bool act[HN_SLOTS];
-    const float *row[HN_SLOTS];
-#pragma unroll
-    for (int t = 0; t < HN_SLOTS; ++t) {
-        int j = g + HN_GROUPS * t;
-        act[t] = j < m;
-        S[t] = 0.f;
-        cmx[t] = 0.f;
-        term[t] = nb - 1;
-        row[t] = a.data + (act[t] ? (int64_t)sm.nbr[j] * a.D : 0) + gl * 4;
-    }
+    bool act = j < m;
+    if (__ballot(act) == 0) return;
+    float S = 0.f, cmx = 0.f;
+    int term = nb - 1;
+    const float *row = a.data + (act ? (int64_t)sm.nbr[j] * a.D : 0) + gl * 4;
     for (int s = 0; s < steps; s += HN_UNROLL) {
-        bool any = false;
-#pragma unroll
-        for (int t = 0; t < HN_SLOTS; ++t) any |= act[t];
-        if (!any) break;
-        float4 v[HN_SLOTS][HN_UNROLL];
+        if (__ballot(act) == 0) break;
         // every load is issued, from a valid address (the row's first step
-        // where the slot is idle or past the end), so that they all go out
+        // where the group is idle or past the end), so that they all go out
         // together before the first is used
+        float4 v[HN_UNROLL];
 #pragma unroll
-        for (int t = 0; t < HN_SLOTS; ++t)
-#pragma unroll
-            for (int u = 0; u < HN_UNROLL; ++u) {
-                const int su = act[t] && s + u < steps ? s + u : 0;
-                v[t][u] = *reinterpret_cast<const float4 *>(row[t] + su * 32);
-            }
+        for (int u = 0; u < HN_UNROLL; ++u) {
+            const int su = act && s + u < steps ? s + u : 0;
+            v[u] = *reinterpret_cast<const float4 *>(row + su * 32);
+        }
 #pragma unroll
         for (int u = 0; u < HN_UNROLL; ++u) {
             if (s + u >= steps) break;
             const float4 qv = *reinterpret_cast<const float4 *>(sm.q + (s + u) * 32 + gl * 4);
-            // the step's test coefficients, shared by the slots
+            // the step's test coefficients
             float cf[BPS], rc[BPS];
 #pragma unroll
             for (int k = 0; k < BPS; ++k) {
                 cf[k] = sm.coef[(s + u) * BPS + k];
                 rc[k] = sm.rcoef[(s + u) * BPS + k];
             }
+            if (!act) continue;
+            const float y0 = v[u].x - qv.x, y1 = v[u].y - qv.y;
+            const float y2 = v[u].z - qv.z, y3 = v[u].w - qv.w;
+            float p = (y0 * y0 + y1 * y1) + (y2 * y2 + y3 * y3);
+            // bsum[k]: the sum over the lanes of block k
+            float bsum[BPS];
+            if constexpr (DD == 8) {
+                p += dpp_xor1(p);                 // pairs: block gl >> 1
+                const float o2 = dpp_xor2(p);
+                // the even and odd block of this lane's quad, then of the other quad
+                const bool odd = (gl & 2) != 0;
+                const float lo = odd ? o2 : p, hi = odd ? p : o2;
+                const float lo4 = dpp_xor4(lo, upper), hi4 = dpp_xor4(hi, upper);
+                bsum[0] = upper ? lo4 : lo;
+                bsum[1] = upper ? hi4 : hi;
+                bsum[BPS > 2 ? 2 : 0] = upper ? lo : lo4;
+                bsum[BPS > 3 ? 3 : 0] = upper ? hi : hi4;
+            } else if constexpr (DD == 16) {
+                p += dpp_xor1(p);
+                p += dpp_xor2(p);                 // quads: block gl >> 2
+                const float o = dpp_xor4(p, upper);
+                bsum[0] = upper ? o : p;
+                bsum[BPS - 1] = upper ? p : o;
+            } else {
+                p += dpp_xor1(p);
+                p += dpp_xor2(p);
+                p += dpp_xor4(p, upper);
+                bsum[0] = p;
+            }
 #pragma unroll
-            for (int t = 0; t < HN_SLOTS; ++t) {
-                if (!act[t]) continue;
-                const float y0 = v[t][u].x - qv.x, y1 = v[t][u].y - qv.y;
-                const float y2 = v[t][u].z - qv.z, y3 = v[t][u].w - qv.w;
-                float p = (y0 * y0 + y1 * y1) + (y2 * y2 + y3 * y3);
-                // bsum[k]: the sum over the lanes of block k
-                float bsum[BPS];
-                if constexpr (DD == 8) {
-                    p += dpp_xor1(p);                 // pairs: block gl >> 1
-                    const float o2 = dpp_xor2(p);
-                    // the even and odd block of this lane's quad, then of the other quad
-                    const bool odd = (gl & 2) != 0;
-                    const float lo = odd ? o2 : p, hi = odd ? p : o2;
-                    const float lo4 = dpp_xor4(lo, upper), hi4 = dpp_xor4(hi, upper);
-                    bsum[0] = upper ? lo4 : lo;
-                    bsum[1] = upper ? hi4 : hi;
-                    bsum[BPS > 2 ? 2 : 0] = upper ? lo : lo4;
-                    bsum[BPS > 3 ? 3 : 0] = upper ? hi : hi4;
-                } else if constexpr (DD == 16) {
-                    p += dpp_xor1(p);
-                    p += dpp_xor2(p);                 // quads: block gl >> 2
-                    const float o = dpp_xor4(p, upper);
-                    bsum[0] = upper ? o : p;
-                    bsum[BPS - 1] = upper ? p : o;
-                } else {
-                    p += dpp_xor1(p);
-                    p += dpp_xor2(p);
-                    p += dpp_xor4(p, upper);
-                    bsum[0] = p;
-                }
-                const int j = g + HN_GROUPS * t;
-#pragma unroll
-                for (int k = 0; k < BPS; ++k) {
-                    const int bi = (s + u) * BPS + k;
-                    S[t] += bsum[k];
-                    if (gl == 0) sm.psum[j * nb + bi] = S[t];
-                    if (bi < nb - 1) {
-                        if (test_reject(S[t], cf[k], r2)) {
-                            term[t] = bi;
-                            act[t] = false;
-                            break;
-                        }
-                        cmx[t] = fmaxf(cmx[t], S[t] * rc[k]);
+            for (int k = 0; k < BPS; ++k) {
+                const int bi = (s + u) * BPS + k;
+                S += bsum[k];
+                if (gl == 0) sm.psum[j * nb + bi] = S;
+                if (bi < nb - 1) {
+                    if (test_reject(S, cf[k], r2)) {
+                        term = bi;
+                        act = false;
+                        break;
                     }
+                    cmx = fmaxf(cmx, S * rc[k]);
                 }
             }
         }
     }
-#pragma unroll
-    for (int t = 0; t < HN_SLOTS; ++t) {
-        int j = g + HN_GROUPS * t;
-        if (j < m && gl == 0) {
-            sm.tb[j] = term[t];
-            sm.cm[j] = cmx[t];
-        }
+    if (j < m && gl == 0) {
+        sm.tb[j] = term;
+        sm.cm[j] = cmx;
     }
 }
 
@@ -420,9 +402,12 @@ __device__ __forceinline__ int outcome_lane(const HnswArgs &a, const Smem &sm, i
 }  // namespace
 
 template <int DD>
-__global__ __launch_bounds__(ADS_WAVE) void hnsw_search_kernel(HnswArgs a) {
+__global__ __launch_bounds__(HN_WAVES * ADS_WAVE) void hnsw_search_kernel(HnswArgs a) {
     extern __shared__ __align__(16) unsigned char hn_smem[];
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & (ADS_WAVE - 1);
+    // the wave index, as a scalar: the two roles below are wave-uniform
+    // branches, so no wave ever meets the other role's barriers
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / ADS_WAVE);
     const int qi = blockIdx.x;
     const int D = a.D, nb = a.nb;
     Smem sm;
@@ -437,8 +422,35 @@ __global__ __launch_bounds__(ADS_WAVE) void hnsw_search_kernel(HnswArgs a) {
         sm.tb = reinterpret_cast<int *>(p); p += HN_MAXDEG * 4;
         sm.cm = reinterpret_cast<float *>(p); p += HN_MAXDEG * 4;
         sm.rcoef = reinterpret_cast<float *>(p); p += ((size_t)nb * 4 + 7) & ~(size_t)7;
+        sm.job = reinterpret_cast<int *>(p); p += 16;
         sm.rx = p;
     }
+    if (wv != 0) {
+        // Waves 1..3 take their share of every DCO phase of wave 0: between
+        // two workgroup barriers wave 0 publishes a phase (or the stop flag),
+        // then all waves evaluate it and meet at a second barrier.
+        for (;;) {
+            __syncthreads();
+            const int stop = __builtin_amdgcn_readfirstlane(sm.job[2]);
+            if (stop) break;
+            const int m = __builtin_amdgcn_readfirstlane(sm.job[0]);
+            const float r2 = __int_as_float(__builtin_amdgcn_readfirstlane(sm.job[1]));
+            dco_phase<DD>(a, sm, m, r2, lane, wv);
+            __syncthreads();
+        }
+        return;
+    }
+    // wave 0: the search.  Every parallel DCO phase goes through run_dco.
+    auto run_dco = [&](int m, float r2) {
+        if (lane == 0) {
+            sm.job[0] = m;
+            sm.job[1] = __float_as_int(r2);
+            sm.job[2] = 0;
+        }
+        __syncthreads();
+        dco_phase<DD>(a, sm, m, r2, lane, 0);
+        __syncthreads();
+    };
     const float *qg = a.qrot + (int64_t)qi * D;
     for (int i = lane; i < D; i += ADS_WAVE) sm.q[i] = qg[i];
     for (int i = lane; i < nb; i += ADS_WAVE) {
@@ -455,8 +467,7 @@ __global__ __launch_bounds__(ADS_WAVE) void hnsw_search_kernel(HnswArgs a) {
     int cur = a.entry;
     if (lane == 0) sm.nbr[0] = cur;
     lds_sync();
-    dco_phase<DD>(a, sm, 1, __builtin_inff(), lane);
-    lds_sync();
+    run_dco(1, __builtin_inff());
     float dcur = sm.psum[nb - 1];
     dcos += 1;
     dims += D;
@@ -471,8 +482,7 @@ __global__ __launch_bounds__(ADS_WAVE) void hnsw_search_kernel(HnswArgs a) {
             if (lane < m) sm.nbr[lane] = v;
             lds_sync();
             const float r0 = dcur;
-            dco_phase<DD>(a, sm, m, r0, lane);
-            lds_sync();
+            run_dco(m, r0);
             bool changed = false;
             for (int j = 0; j < m; ++j) {
                 bool pos;
@@ -488,7 +498,7 @@ __global__ __launch_bounds__(ADS_WAVE) void hnsw_search_kernel(HnswArgs a) {
                 }
             }
             lds_sync();
-            if (!changed) break;
+            if (!__builtin_amdgcn_readfirstlane(changed ? 1 : 0)) break;
         }
     }
 
@@ -543,8 +553,7 @@ __global__ __launch_bounds__(ADS_WAVE) void hnsw_search_kernel(HnswArgs a) {
             return nr < a.nef ? __builtin_inff() : key_dist2(rmaxk);
         };
         const float r0 = threshold();
-        dco_phase<DD>(a, sm, m, r0, lane);
-        lds_sync();
+        run_dco(m, r0);
         // Replay of the sequential loop: all remaining neighbours are
         // evaluated at the current threshold at once (lane = neighbour); the
         // first one whose outcome changes a set ("hot") is then applied, the
@@ -599,6 +608,10 @@ __global__ __launch_bounds__(ADS_WAVE) void hnsw_search_kernel(HnswArgs a) {
         }
     }
 
+    // release the other waves
+    if (lane == 0) sm.job[2] = 1;
+    __syncthreads();
+
     // answer: the K nearest of R (HNSW, HNSW+; every member is expanded now,
     // flag 1, and is taken out in ascending order) or R1 (HNSW++, sorted)
     for (int k = 0; k < a.K; ++k) {
@@ -644,7 +657,7 @@ __global__ void hnsw_setup_kernel(float *coef, int nb, int dd, int D, double eps
 
 size_t hnsw_smem_bytes(int D, int nb, int nef, int K) {
     size_t b = (size_t)D * 4 + (size_t)HN_MAXDEG * nb * 4 + 2 * (((size_t)nb * 4 + 7) & ~(size_t)7) +
-               (size_t)nef * 8 + (size_t)K * 8 + 3 * HN_MAXDEG * 4 + (size_t)nef;
+               (size_t)nef * 8 + (size_t)K * 8 + 3 * HN_MAXDEG * 4 + 16 + (size_t)nef;
     return (b + 15) & ~(size_t)15;
 }
 
@@ -662,9 +675,9 @@ hipError_t launch_hnsw_search(const HnswArgs &a, int nq, hipStream_t s) {
     if (nq <= 0) return hipSuccess;
     const size_t smem = hnsw_smem_bytes(a.D, a.nb, a.nef, a.K);
     switch (a.dd) {
-        case 8: hipLaunchKernelGGL(hnsw_search_kernel<8>, dim3((unsigned)nq), dim3(ADS_WAVE), smem, s, a); break;
-        case 16: hipLaunchKernelGGL(hnsw_search_kernel<16>, dim3((unsigned)nq), dim3(ADS_WAVE), smem, s, a); break;
-        case 32: hipLaunchKernelGGL(hnsw_search_kernel<32>, dim3((unsigned)nq), dim3(ADS_WAVE), smem, s, a); break;
+        case 8: hipLaunchKernelGGL(hnsw_search_kernel<8>, dim3((unsigned)nq), dim3(HN_WAVES * ADS_WAVE), smem, s, a); break;
+        case 16: hipLaunchKernelGGL(hnsw_search_kernel<16>, dim3((unsigned)nq), dim3(HN_WAVES * ADS_WAVE), smem, s, a); break;
+        case 32: hipLaunchKernelGGL(hnsw_search_kernel<32>, dim3((unsigned)nq), dim3(HN_WAVES * ADS_WAVE), smem, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
