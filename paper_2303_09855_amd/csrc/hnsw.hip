@@ -33,6 +33,8 @@ constexpr int HN_LANES = 8;        // lanes per neighbour: 8 x float4 = 32 coord
 constexpr int HN_GROUPS = ADS_WAVE / HN_LANES;
 constexpr int HN_WAVES = 4;        // waves per query: wave 0 searches, every wave DCOs 8 neighbours
 constexpr int HN_UNROLL = 8;       // steps of 32 coordinates loaded at once
+constexpr int HN_TOP = 4;          // largest keys of its stripe of R kept by each lane
+constexpr int HN_BATCH = 4;        // set entries per lane read at once by the scans of R
 static_assert(HN_GROUPS * HN_WAVES == HN_MAXDEG, "one neighbour per lane group and wave");
 
 __device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
@@ -506,13 +508,80 @@ __global__ __launch_bounds__(HN_WAVES * ADS_WAVE) void hnsw_search_kernel(HnswAr
     uint32_t *vis = a.visited + (int64_t)qi * a.vis_words;
     if (lane == 0) atomicOr(vis + (cur >> 5), 1u << (cur & 31));
     // R (R2 for HNSW++) is kept unsorted: a pop takes the smallest key not yet
-    // expanded, and a full set keeps its largest key (the threshold and the
-    // entry an insertion replaces) in rmaxk / rmaxi; both come from one pass
-    // over the set and a wave reduction.  R1 (K entries) stays sorted.
+    // expanded (one pass over the set and a wave reduction), and a full set
+    // keeps its largest key (the threshold and the entry an insertion
+    // replaces) in rmaxk / rmaxi.  For the largest key, lane l keeps in
+    // registers the HN_TOP largest keys of its stripe (entries i = l mod 64),
+    // or fewer: tn of them, always the tn largest of the stripe.  The largest
+    // key of R is then a wave reduction over the stripes' first keys.  An
+    // insertion replaces the largest key in place, so only that stripe
+    // changes: its first key leaves the list and the new key enters it when it
+    // is above the list's last one.  A stripe whose list runs empty makes every
+    // lane re-read its stripe.  R1 (K entries) stays sorted.
     int nr = 0, nr1 = 0;
     uint64_t rmaxk = KEY_NONE;
     int rmaxi = -1;
     const bool pp = a.variant == ADS_HNSW_PP;
+    uint64_t tl[HN_TOP];
+    int ti[HN_TOP];
+    int tn = 0;
+    // the list's last (smallest) key; 0 when empty
+    auto tl_last = [&]() {
+        uint64_t k = 0;
+#pragma unroll
+        for (int c = 0; c < HN_TOP; ++c)
+            if (c == tn - 1) k = tl[c];
+        return k;
+    };
+    // key (at slot idx of R) enters this lane's list: appended when there is
+    // room, else in place of the last key when above it; then moved up to its
+    // place (descending order)
+    auto tl_add = [&](uint64_t key, int idx) {
+        if (tn == HN_TOP) {
+            if (key <= tl[HN_TOP - 1]) return;
+            tl[HN_TOP - 1] = key;
+            ti[HN_TOP - 1] = idx;
+        } else {
+#pragma unroll
+            for (int c = 0; c < HN_TOP; ++c)
+                if (c == tn) {
+                    tl[c] = key;
+                    ti[c] = idx;
+                }
+            ++tn;
+        }
+#pragma unroll
+        for (int c = HN_TOP - 1; c >= 1; --c)
+            if (c < tn && tl[c] > tl[c - 1]) {
+                const uint64_t tk = tl[c];
+                tl[c] = tl[c - 1];
+                tl[c - 1] = tk;
+                const int tx = ti[c];
+                ti[c] = ti[c - 1];
+                ti[c - 1] = tx;
+            }
+    };
+    auto stripes_reread = [&]() {
+        tn = 0;
+        for (int i0 = lane; i0 < nr; i0 += HN_BATCH * ADS_WAVE) {
+            uint64_t v[HN_BATCH];
+#pragma unroll
+            for (int c = 0; c < HN_BATCH; ++c) {
+                const int i = i0 + c * ADS_WAVE;
+                v[c] = i < nr ? sm.rk[i] : 0;
+            }
+#pragma unroll
+            for (int c = 0; c < HN_BATCH; ++c)
+                if (i0 + c * ADS_WAVE < nr) tl_add(v[c], i0 + c * ADS_WAVE);
+        }
+    };
+    auto max_of_stripes = [&]() {
+        uint64_t k = tn > 0 ? tl[0] : 0;
+        int i = tn > 0 ? ti[0] : -1;
+        wave_best(k, i, [](uint64_t ok, int oi, uint64_t kk, int ii) { return oi >= 0 && (ii < 0 || ok > kk); });
+        rmaxk = k;
+        rmaxi = i;
+    };
     auto r_insert = [&](uint64_t key) {
         const int at = nr < a.nef ? nr : rmaxi;
         if (lane == 0) {
@@ -520,8 +589,31 @@ __global__ __launch_bounds__(HN_WAVES * ADS_WAVE) void hnsw_search_kernel(HnswAr
             sm.rx[at] = 0;
         }
         lds_sync();
-        if (nr < a.nef) ++nr;
-        if (nr == a.nef) rmaxi = argmax_all(sm.rk, nr, lane, &rmaxk);
+        if (nr < a.nef) {
+            ++nr;
+            if (nr == a.nef) {
+                stripes_reread();
+                max_of_stripes();
+            }
+        } else {
+            if (lane == (at & (ADS_WAVE - 1))) {
+                // the stripe's first key was R's largest, at slot at
+#pragma unroll
+                for (int c = 0; c + 1 < HN_TOP; ++c) {
+                    tl[c] = tl[c + 1];
+                    ti[c] = ti[c + 1];
+                }
+                --tn;
+                // the new key belongs to the list only when it is above the
+                // list's last key: below it, keys of the stripe outside the
+                // list may be larger
+                if (tn > 0 && key > tl_last()) tl_add(key, at);
+            }
+            // a stripe with entries and an empty list: re-read every stripe
+            const bool has = lane < nr;
+            if (__ballot(has && tn == 0)) stripes_reread();
+            max_of_stripes();
+        }
     };
     r_insert(make_key(dcur, (uint32_t)cur));
     if (pp) sorted_insert(sm.r1k, nullptr, nr1, a.K, make_key(dcur, (uint32_t)cur), lane);
