@@ -34,6 +34,7 @@ constexpr int HN_GROUPS = ADS_WAVE / HN_LANES;
 constexpr int HN_WAVES = 4;        // waves per query: wave 0 searches, every wave DCOs 8 neighbours
 constexpr int HN_UNROLL = 8;       // steps of 32 coordinates loaded at once
 constexpr int HN_TOP = 4;          // largest keys of its stripe of R kept by each lane
+constexpr int HN_BOT = 4;          // smallest unexpanded keys of its stripe of R kept by each lane
 constexpr int HN_BATCH = 4;        // set entries per lane read at once by the scans of R
 static_assert(HN_GROUPS * HN_WAVES == HN_MAXDEG, "one neighbour per lane group and wave");
 
@@ -561,6 +562,82 @@ __global__ __launch_bounds__(HN_WAVES * ADS_WAVE) void hnsw_search_kernel(HnswAr
                 ti[c - 1] = tx;
             }
     };
+    // Likewise for pops: lane l keeps the bn smallest unexpanded keys of its
+    // stripe (bn <= HN_BOT, ascending) and the count ucnt of unexpanded
+    // entries there; the pop is a wave reduction over the lists' first keys.
+    uint64_t bl[HN_BOT];
+    int bx[HN_BOT];
+    int bn = 0, ucnt = 0;
+    auto bl_last = [&]() {
+        uint64_t k = KEY_NONE;
+#pragma unroll
+        for (int c = 0; c < HN_BOT; ++c)
+            if (c == bn - 1) k = bl[c];
+        return k;
+    };
+    // key (at slot idx) enters this lane's list: appended when there is
+    // room, else in place of the last key when below it; then moved down to
+    // its place (ascending order)
+    auto bl_add = [&](uint64_t key, int idx) {
+        if (bn == HN_BOT) {
+            if (key >= bl[HN_BOT - 1]) return;
+            bl[HN_BOT - 1] = key;
+            bx[HN_BOT - 1] = idx;
+        } else {
+#pragma unroll
+            for (int c = 0; c < HN_BOT; ++c)
+                if (c == bn) {
+                    bl[c] = key;
+                    bx[c] = idx;
+                }
+            ++bn;
+        }
+#pragma unroll
+        for (int c = HN_BOT - 1; c >= 1; --c)
+            if (c < bn && bl[c] < bl[c - 1]) {
+                const uint64_t tk = bl[c];
+                bl[c] = bl[c - 1];
+                bl[c - 1] = tk;
+                const int tx = bx[c];
+                bx[c] = bx[c - 1];
+                bx[c - 1] = tx;
+            }
+    };
+    // removes entry c (< bn) of this lane's list
+    auto bl_drop = [&](int c0) {
+#pragma unroll
+        for (int c = 0; c + 1 < HN_BOT; ++c)
+            if (c >= c0) {
+                bl[c] = bl[c + 1];
+                bx[c] = bx[c + 1];
+            }
+        --bn;
+    };
+    auto unexpanded_reread = [&]() {
+        bn = 0;
+        ucnt = 0;
+        for (int i0 = lane; i0 < nr; i0 += HN_BATCH * ADS_WAVE) {
+            uint64_t v[HN_BATCH];
+            bool u[HN_BATCH];
+#pragma unroll
+            for (int c = 0; c < HN_BATCH; ++c) {
+                const int i = i0 + c * ADS_WAVE;
+                u[c] = i < nr;
+                v[c] = u[c] ? sm.rk[i] : KEY_NONE;
+                u[c] = u[c] && sm.rx[i] == 0;
+            }
+#pragma unroll
+            for (int c = 0; c < HN_BATCH; ++c)
+                if (u[c]) {
+                    ++ucnt;
+                    bl_add(v[c], i0 + c * ADS_WAVE);
+                }
+        }
+    };
+    // a stripe with unexpanded entries and an empty list: re-read every stripe
+    auto unexpanded_check = [&]() {
+        if (__ballot(bn == 0 && ucnt > 0)) unexpanded_reread();
+    };
     auto stripes_reread = [&]() {
         tn = 0;
         for (int i0 = lane; i0 < nr; i0 += HN_BATCH * ADS_WAVE) {
@@ -584,6 +661,24 @@ __global__ __launch_bounds__(HN_WAVES * ADS_WAVE) void hnsw_search_kernel(HnswAr
     };
     auto r_insert = [&](uint64_t key) {
         const int at = nr < a.nef ? nr : rmaxi;
+        const bool owner = lane == (at & (ADS_WAVE - 1));
+        if (nr >= a.nef && owner && sm.rx[at] == 0) {
+            // the entry replaced was not expanded yet
+            --ucnt;
+            int f = -1;
+#pragma unroll
+            for (int c = 0; c < HN_BOT; ++c)
+                if (c < bn && bx[c] == at) f = c;
+            if (f >= 0) bl_drop(f);
+        }
+        if (owner) {
+            // the new key joins the list when the list holds every unexpanded
+            // entry of the stripe, or when it is below the list's last key
+            const bool complete = bn == ucnt;
+            ++ucnt;
+            if (complete || (bn > 0 && key < bl_last())) bl_add(key, at);
+        }
+        lds_sync();
         if (lane == 0) {
             sm.rk[at] = key;
             sm.rx[at] = 0;
@@ -614,17 +709,25 @@ __global__ __launch_bounds__(HN_WAVES * ADS_WAVE) void hnsw_search_kernel(HnswAr
             if (__ballot(has && tn == 0)) stripes_reread();
             max_of_stripes();
         }
+        unexpanded_check();
     };
     r_insert(make_key(dcur, (uint32_t)cur));
     if (pp) sorted_insert(sm.r1k, nullptr, nr1, a.K, make_key(dcur, (uint32_t)cur), lane);
     lds_sync();
     for (;;) {
         // pop: the nearest member of R not expanded yet
-        uint64_t pkey;
-        const int p = argmin_flag(sm.rk, sm.rx, nr, 0, lane, &pkey);
+        uint64_t pkey = bn > 0 ? bl[0] : KEY_NONE;
+        int p = bn > 0 ? bx[0] : -1;
+        wave_best(pkey, p, [](uint64_t ok, int, uint64_t k, int) { return ok < k; });
         if (p < 0) break;
+        if (lane == (p & (ADS_WAVE - 1))) {
+            bl_drop(0);
+            --ucnt;
+        }
         lds_sync();
         if (lane == 0) sm.rx[p] = 1;
+        lds_sync();
+        unexpanded_check();
         hops += 1;
         const int u = key_id(pkey);
         // neighbours not visited yet, in stored order
