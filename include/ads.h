@@ -39,7 +39,7 @@ typedef enum {
     ADS_EINVAL = -1,        /* invalid argument (message in ads_last_error) */
     ADS_ENOMEM = -2,        /* device or host allocation failed */
     ADS_EHIP = -3,          /* HIP runtime / launch error */
-    ADS_EUNSUPPORTED = -4   /* valid request this build does not support */
+    ADS_EUNSUPPORTED = -4   /* valid request the library does not support */
 } ads_status;
 
 typedef enum {

@@ -3,12 +3,12 @@
 // result set R) and HNSW++ (Section 5.1: R1 of K exact distances supplies the
 // DCO threshold and the answer; R2 of N_ef observed distances drives the beam).
 //
-// One wave per query.  The search is a chain of dependent steps, so the
-// parallelism inside a query is the neighbour list of the vertex being
-// expanded: its not-yet-visited neighbours (up to 32) are DCO'd together, 8
-// lanes per neighbour and 4 neighbours per lane group in flight, against the
-// threshold that holds when the expansion starts, and the partial sum after
-// every block of delta_d coordinates is kept in LDS.  The sequential semantics
+// One workgroup of four waves per query.  The search is a chain of dependent
+// steps, run by wave 0, so the parallelism inside a query is the neighbour
+// list of the vertex being expanded: its not-yet-visited neighbours (up to 32)
+// are DCO'd together by the four waves (8 neighbours each, 8 lanes per
+// neighbour), against the threshold that holds when the expansion starts, and
+// the partial sum after every block of delta_d coordinates is kept in LDS.  The sequential semantics
 // (the threshold may shrink after each insertion) are then replayed neighbour
 // by neighbour from those partial sums: a smaller threshold can only move a
 // rejection to an earlier block (the test compares S_d with coef(d) r^2), so
@@ -21,8 +21,9 @@
 // keys an evicted member can never be expanded later, because R's largest key
 // only shrinks once R is full, so popping the smallest unexpanded member of R
 // and stopping when none is left expands exactly what the two-heap loop
-// expands.  R is unsorted (pops and the largest key by reductions), R1 is a
-// sorted array.  The threshold is +inf until the set is full.
+// expands.  R is unsorted (pops and the largest key by wave reductions over
+// per-lane lists of its stripes), R1 is a sorted array.  The threshold is +inf
+// until the set is full.
 #include "kernels.h"
 
 namespace ads {
