@@ -108,6 +108,8 @@ def integer_graph(ads):
     (0, 2.1, 8, 1, 1),
     (0, 2.1, 16, 10, 2000),
     (2, 2.1, 16, 100, 120),
+    (1, math.inf, 16, 10, 3000),     # R fills: 47 entries per lane stripe
+    (0, 2.1, 16, 10, 4096),          # the largest beam: every vertex enters R
 ])
 def test_integer_data_is_bit_exact(ads, integer_graph, variant, eps0, dd, K, nef):
     x, q, g = integer_graph
