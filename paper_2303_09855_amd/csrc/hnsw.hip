@@ -756,25 +756,35 @@ __global__ __launch_bounds__(HN_WAVES * ADS_WAVE) void hnsw_search_kernel(HnswAr
         // threshold re-read, and the evaluation repeats after it.  Neighbours
         // before the hot one change nothing, so their outcomes at this
         // threshold are the sequential ones.
+        // A lane's outcome depends only on its neighbour and the threshold, so
+        // it is evaluated again only when the threshold has changed (HNSW++'s
+        // threshold comes from R1, which R2's insertions leave alone).
         int j = 0;
+        int stop = 0;
+        bool pos = false;
+        float sv = 0.f, obs = 0.f;
+        uint32_t w_lane = 0;
+        float r2_eval = __builtin_nanf("");
         while (j < m) {
             const float r2 = threshold();
             const bool full = nr >= a.nef, full1 = nr1 >= a.K;
             const uint64_t rmax = full ? rmaxk : KEY_NONE;
             const uint64_t r1max = pp && full1 ? sm.r1k[nr1 - 1] : KEY_NONE;
-            int stop = 0;
-            bool pos = false, hot = false;
-            float sv = 0.f;
-            if (lane >= j && lane < m) {
-                stop = outcome_lane(a, sm, lane, r2, r0, &pos, &sv);
-                const uint32_t w = (uint32_t)sm.nbr[lane];
-                const int d = (stop + 1) * dd;
-                if (!pp) {
-                    hot = pos && make_key(sv, w) < rmax;
-                } else {
-                    const float obs = d == D ? sv : (float)((double)sv * (double)D / (double)d);
-                    hot = (pos && make_key(sv, w) < r1max) || make_key(obs, w) < rmax;
+            if (!(r2 == r2_eval)) {
+                if (lane >= j && lane < m) {
+                    stop = outcome_lane(a, sm, lane, r2, r0, &pos, &sv);
+                    w_lane = (uint32_t)sm.nbr[lane];
+                    const int d = (stop + 1) * dd;
+                    obs = d == D ? sv : (float)((double)sv * (double)D / (double)d);
                 }
+                r2_eval = r2;
+            }
+            bool hot = false;
+            if (lane >= j && lane < m) {
+                if (!pp)
+                    hot = pos && make_key(sv, w_lane) < rmax;
+                else
+                    hot = (pos && make_key(sv, w_lane) < r1max) || make_key(obs, w_lane) < rmax;
             }
             const uint64_t hm = wave_ballot(hot);
             const int k = hm ? __ffsll((long long)hm) - 1 : m;
@@ -795,8 +805,7 @@ __global__ __launch_bounds__(HN_WAVES * ADS_WAVE) void hnsw_search_kernel(HnswAr
                     const uint64_t key = make_key(s, w);
                     if (key < r1max) sorted_insert(sm.r1k, nullptr, nr1, a.K, key, lane);
                 }
-                const float obs = d == D ? s : (float)((double)s * (double)D / (double)d);
-                const uint64_t key2 = make_key(obs, w);
+                const uint64_t key2 = make_key(lane_value(obs, k), w);
                 if (key2 < rmax) r_insert(key2);
             }
             lds_sync();
