@@ -304,48 +304,25 @@ __device__ __forceinline__ void wave_best(uint64_t &k, int &i, Better better) {
 __device__ int argmin_flag(const uint64_t *k, const uint8_t *x, int n, uint8_t want, int lane, uint64_t *kout) {
     uint64_t best = KEY_NONE;
     int bi = -1;
-    // four entries per lane are read before any is compared
-    for (int i0 = lane; i0 < n; i0 += 4 * ADS_WAVE) {
-        uint64_t v[4];
-        bool ok[4];
+    // HN_BATCH entries per lane are read before any is compared
+    for (int i0 = lane; i0 < n; i0 += HN_BATCH * ADS_WAVE) {
+        uint64_t v[HN_BATCH];
+        bool ok[HN_BATCH];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < HN_BATCH; ++c) {
             const int i = i0 + c * ADS_WAVE;
             ok[c] = i < n;
             v[c] = ok[c] ? k[i] : KEY_NONE;
             ok[c] = ok[c] && x[i] == want;
         }
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+        for (int c = 0; c < HN_BATCH; ++c)
             if (ok[c] && v[c] < best) {
                 best = v[c];
                 bi = i0 + c * ADS_WAVE;
             }
     }
     wave_best(best, bi, [](uint64_t ok, int, uint64_t k, int) { return ok < k; });
-    *kout = best;
-    return bi;
-}
-
-// Largest key of k[0..n) (n >= 1) and its index, the same on every lane.
-__device__ int argmax_all(const uint64_t *k, int n, int lane, uint64_t *kout) {
-    uint64_t best = 0;
-    int bi = -1;
-    for (int i0 = lane; i0 < n; i0 += 4 * ADS_WAVE) {
-        uint64_t v[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int i = i0 + c * ADS_WAVE;
-            v[c] = i < n ? k[i] : 0;
-        }
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-            if (i0 + c * ADS_WAVE < n && (bi < 0 || v[c] > best)) {
-                best = v[c];
-                bi = i0 + c * ADS_WAVE;
-            }
-    }
-    wave_best(best, bi, [](uint64_t ok, int oi, uint64_t k, int i) { return oi >= 0 && (i < 0 || ok > k); });
     *kout = best;
     return bi;
 }
