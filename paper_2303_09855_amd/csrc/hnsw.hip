@@ -37,6 +37,7 @@ constexpr int HN_UNROLL = 8;       // steps of 32 coordinates loaded at once
 constexpr int HN_TOP = 4;          // largest keys of its stripe of R kept by each lane
 constexpr int HN_BOT = 4;          // smallest unexpanded keys of its stripe of R kept by each lane
 constexpr int HN_BATCH = 4;        // set entries per lane read at once by the scans of R
+constexpr int HN_REPLAY = 8;       // stored block sums per lane read at once by the replay
 static_assert(HN_GROUPS * HN_WAVES == HN_MAXDEG, "one neighbour per lane group and wave");
 
 __device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
@@ -356,18 +357,18 @@ __device__ __forceinline__ int outcome_lane(const HnswArgs &a, const Smem &sm, i
     if (r2 != r2_phase && !no_test_below(sm, j, t0, nb, r2)) {
         const int lim = t0 < nb - 1 ? t0 : nb - 2;     // blocks that carry a test
         stop = nb - 1;
-        // four blocks are read before any is tested
-        for (int b0 = 0; b0 <= lim; b0 += 4) {
-            float ps[4], cf[4];
+        // HN_REPLAY blocks are read before any is tested
+        for (int b0 = 0; b0 <= lim; b0 += HN_REPLAY) {
+            float ps[HN_REPLAY], cf[HN_REPLAY];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
+            for (int c = 0; c < HN_REPLAY; ++c) {
                 const int b = b0 + c <= lim ? b0 + c : lim;
                 ps[c] = sm.psum[j * nb + b];
                 cf[c] = sm.coef[b];
             }
             int hit = -1;
 #pragma unroll
-            for (int c = 3; c >= 0; --c)
+            for (int c = HN_REPLAY - 1; c >= 0; --c)
                 if (b0 + c <= lim && test_reject(ps[c], cf[c], r2)) hit = b0 + c;
             if (hit >= 0) {
                 stop = hit;
